@@ -1,0 +1,171 @@
+"""Throughput benchmark of the haemoglobin-estimation hot path on one MI355X.
+
+One step = one hb_estimate_frames call over a batch of synthetic 1920x1080
+frames (log-attenuation + 2-level Haar + Tikhonov, posterior over a 256x256
+THb x SO2 grid, inverse Haar and maps), frames already resident in HBM.
+
+Prints one JSON line with frames/s (value), Mpixel/s, the roofline of the
+dominant kernel (the posterior) from per-kernel HIP events recorded on the
+launch stream, and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frames/s + Mpixel/s at 1920x1080 on 1 GPU; p99 frame latency, 16 streams"
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Algorithmic operations per (LL pixel, grid node) pair of the posterior:
+# 3 sub + 3 mul + 2 add (squared distance), 1 mul (-1/(2 sigma^2)), 1 sub (max
+# offset), 1 add + 2 mul + 2 add (three moments) = 15 flops, plus one exp.
+FLOPS_PER_PAIR = 15
+EXPS_PER_PAIR = 1
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--levels", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--split", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample (0 = skip)")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg, quiet=False):
+    if not quiet:
+        print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(target_s: float, levels: int, grid: int, quiet: bool):
+    """Time the FP64 oracle on whole-width row bands of video frame 0."""
+    from oracle import hb_oracle as orc
+    from paper_1706_07263_amd import synth
+    from tests import hbtest
+    w = synth.config3((0,))
+    s = dict(w.plan)
+    s["levels"], s["grid_thb"], s["grid_so2"] = levels, grid, grid
+    b = 1 << levels
+    fr = w.frames.astype(np.float64)
+    model = hbtest.oracle_model(synth.spectra())
+    # calibration on a small band, then a band sized for the target time
+    rows = 4 * b
+    t0 = time.perf_counter()
+    orc.estimate(hbtest.oracle_params(1920, rows, s), model, fr[:, :rows])
+    dt = time.perf_counter() - t0
+    rows = int(min(1080, max(b, rows * target_s / max(dt, 1e-3)))) // b * b
+    rows = max(rows, b)
+    t0 = time.perf_counter()
+    orc.estimate(hbtest.oracle_params(1920, rows, s), model, fr[:, :rows])
+    dt = time.perf_counter() - t0
+    frac = rows / 1080.0
+    log(f"cpu oracle: {rows} rows x 1920 in {dt:.2f} s on {orc.threads()} threads", quiet)
+    return {"value": frac / dt, "unit": "frames/s", "cores": orc.threads(), "kind": "oracle",
+            "sample": f"rows 0..{rows - 1} of frame 0 (1920x{rows} px, "
+                      f"{(rows // b) * (1920 // b)} low-pass pixels x {grid * grid} nodes), "
+                      f"{dt:.2f} s, scaled by {rows}/1080"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported by this build "
+              "(each frame and each stream is independent: see the sharding notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1706_07263_amd import build as hb_build
+    if not os.path.exists(hb_build.LIB):
+        import __graft_entry__
+        __graft_entry__.build()
+    from paper_1706_07263_amd import hb, synth
+    from tests import hbtest
+
+    B = a.batch
+    H, W = 1080, 1920
+    log(f"generating {B} synthetic 1080p frames", a.quiet)
+    idx = [int(i * 300 / B) for i in range(B)]
+    wl = synth.config3(idx, dtype=a.dtype)
+    settings = dict(wl.plan)
+    settings["levels"], settings["grid_thb"], settings["grid_so2"] = a.levels, a.grid, a.grid
+
+    dev = torch.device("cuda:0")
+    frames = hbtest.to_device(wl.frames, a.dtype)
+    maps = [torch.empty((B, H, W), device=dev, dtype=torch.float32) for _ in range(4)]
+    desc = hb.make_desc(W, H, levels=a.levels, dtype=a.dtype, max_batch=B, grid_thb=a.grid,
+                        grid_so2=a.grid, lam=settings["lam"], sigma=settings["sigma"], grid_split=a.split)
+    plan = hb.Plan(desc, 0).set_forward_model(synth.spectra())
+    info = plan.info()
+    stream = torch.cuda.Stream(dev)
+
+    log(f"warmup {a.warmup}", a.quiet)
+    with torch.cuda.stream(stream):
+        for _ in range(a.warmup):
+            plan.estimate(frames, maps, stream)
+    torch.cuda.synchronize()
+
+    hb.hb_plan_set_timing(plan.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(a.steps):
+            plan.estimate(frames, maps, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms, launches = hb.hb_plan_get_timing(plan.handle)
+    hb.hb_plan_set_timing(plan.handle, False)
+    log(f"timed {a.steps} steps in {elapsed:.3f} s; stage ms {ms / np.maximum(launches, 1)}", a.quiet)
+
+    fps = a.steps * B / elapsed
+    LL = (H >> a.levels) * (W >> a.levels)
+    pairs_per_launch = B * LL * a.grid * a.grid
+    k2_s = ms[1] / max(launches[1], 1) / 1e3
+    achieved = pairs_per_launch * FLOPS_PER_PAIR / k2_s / 1e12
+    roofline = {"bound": "alu", "kernel": "k_posterior", "achieved": round(achieved, 3),
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": None, "avg_launch_ms": round(k2_s * 1e3, 4),
+                "pairs_per_s": pairs_per_launch / k2_s,
+                "flops_per_pair": FLOPS_PER_PAIR, "exps_per_pair": EXPS_PER_PAIR}
+    stage = {"log_haar_ms": ms[0] / max(launches[0], 1), "posterior_ms": ms[1] / max(launches[1], 1),
+             "recompose_ms": ms[2] / max(launches[2], 1), "call_ms": ms[3] / max(launches[3], 1)}
+    hbm_bytes = B * H * W * (12 if a.dtype == "f32" else 6) + B * H * W * 16
+    stage["log_haar_plus_recompose_GBps"] = hbm_bytes / ((stage["log_haar_ms"] + stage["recompose_ms"]) * 1e-3) / 1e9
+
+    cpu = None
+    if a.cpu_seconds > 0:
+        cpu = cpu_baseline(a.cpu_seconds, a.levels, a.grid, a.quiet)
+
+    out = {
+        "metric": METRIC, "value": round(fps, 3), "unit": "frames/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(elapsed / a.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": a.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"1920x1080 video frames, {a.levels} Haar levels, {a.grid}x{a.grid} "
+                               f"THb x SO2 posterior grid, {a.dtype} frames",
+                   "global_batch": B, "frame": "1920x1080", "levels": a.levels,
+                   "grid": f"{a.grid}x{a.grid}", "grid_split": info["grid_split"], "parallelism": "1 GPU"},
+        "mpixel_per_s": round(fps * H * W / 1e6, 2),
+        "stages_ms_per_call": {k: round(v, 4) for k, v in stage.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

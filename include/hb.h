@@ -1,0 +1,172 @@
+/*
+ * hb.h - C ABI of the MI355X (gfx950) haemoglobin-estimation library.
+ *
+ * Implements the per-frame path of Jones et al., "Fast Estimation of
+ * Haemoglobin Concentration in Tissue Via Wavelet Decomposition"
+ * (arXiv 1706.07263), Method section:
+ *   1. RGB log-attenuation y = -ln(max(I, floor));
+ *   2. n-level 2D Haar transform of each channel (Eq. 1-2, 2x2 windows);
+ *   3. Tikhonov inversion of every directional coefficient to (Hb, HbO2)
+ *      with M = (E'E + gamma I)^-1 E' (Eq. 5 with the camera matrix replaced
+ *      by E, the Jacobian of the RGB forward model at a reference point);
+ *   4. on the low-pass band, the posterior mean of (Hb, HbO2) over a
+ *      THb x SO2 grid, Gaussian likelihood on the block-mean log-attenuation
+ *      through the nonlinear forward model, uniform prior over the nodes
+ *      (the paper applies a Bayesian estimator to this band; the low-pass
+ *      coefficients behave as a lower-resolution image);
+ *   5. inverse Haar (Eq. 4: H is its own inverse) to full-resolution Hb, HbO2,
+ *      and the derived maps THb = Hb + HbO2, SO2 = HbO2 / THb (Fig. 1).
+ *
+ * Conventions
+ *   - Every function returns hb_status_t; no exception or abort crosses the ABI.
+ *   - Argument, shape and state errors are detected on the host before any
+ *     device work; nothing is launched when a call fails.
+ *   - Device pointers are plain HIP device addresses (e.g. a PyTorch tensor's
+ *     data_ptr()); the caller owns frames and output maps.  The plan owns its
+ *     tables and scratch, all allocated in hb_plan_create/hb_set_forward_model.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - A plan is bound to one device and is not re-entrant: calls that use the
+ *     same plan on different streams must be ordered by the caller.
+ */
+#ifndef HB_H
+#define HB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HB_OK = 0,
+    HB_ERR_INVALID_ARG = -1,      /* NULL pointer, value out of range            */
+    HB_ERR_SHAPE = -2,            /* frame size not divisible by 2^levels, ...   */
+    HB_ERR_NO_FORWARD_MODEL = -3, /* hb_estimate_frames before the model is set  */
+    HB_ERR_OUT_OF_MEMORY = -4,    /* device allocation failed                    */
+    HB_ERR_DEVICE = -5,           /* a HIP call or kernel launch failed          */
+    HB_ERR_ILL_POSED = -6,        /* E'E + gamma I is singular                   */
+    HB_ERR_BATCH = -7             /* n_frames > max_batch                        */
+} hb_status_t;
+
+typedef enum { HB_F32 = 0, HB_F16 = 1, HB_BF16 = 2 } hb_dtype_t;
+
+/* Estimator on the low-pass band.  TIKHONOV applies the linearised inverse there
+ * too (the paper notes Tikhonov can be used on any Haar coefficient); it is a
+ * diagnostic mode: the whole path then reduces to one affine map per pixel. */
+typedef enum { HB_LOWPASS_BAYES = 0, HB_LOWPASS_TIKHONOV = 1 } hb_lowpass_t;
+
+typedef struct hb_plan_s *hb_plan_t;
+
+/* Plan descriptor.  Fill with hb_plan_desc_default, then override. */
+typedef struct {
+    int32_t width, height;      /* frame size in pixels; both divisible by 2^levels      */
+    int32_t levels;             /* Haar levels n, 0..5 (0 = posterior on every pixel)    */
+    int32_t frame_dtype;        /* hb_dtype_t of the stored intensities                   */
+    int32_t max_batch;          /* largest n_frames per hb_estimate_frames call (>= 1)   */
+    int32_t grid_thb, grid_so2; /* posterior grid nodes along THb and SO2 (1..4096 each) */
+    double thb_min, thb_max;    /* uM, inclusive linspace                                  */
+    double so2_min, so2_max;    /* fraction in [0, 1], inclusive linspace                  */
+    double lambda;              /* Tikhonov gamma relative to tr(E'E)/2 (>= 0)             */
+    double sigma;               /* likelihood s.d. in natural-log attenuation units (> 0) */
+    double intensity_floor;     /* intensities below it are clamped before the log (> 0) */
+    double ref_thb, ref_so2;    /* linearisation point of E; NaN = grid centre            */
+    double thb_eps;             /* SO2 is NaN where THb <= thb_eps (uM)                    */
+    int32_t lowpass;            /* hb_lowpass_t                                            */
+    int32_t grid_split;         /* posterior grid split across workgroups; 0 = automatic   */
+} hb_plan_desc_t;
+
+/* Camera sensitivities and attenuation spectra (the camera matrix C and the
+ * coefficients xi of the Method section).  Copied by hb_set_forward_model. */
+typedef struct {
+    int32_t n_wavelengths;
+    const double *wavelength_nm;  /* [n], informational, may be NULL               */
+    const double *eps_hb;         /* [n] cm^-1 uM^-1, natural-log units             */
+    const double *eps_hbo2;       /* [n]                                            */
+    const double *response;       /* [3][n] R, G, B; each row normalised to unit sum */
+    double path_length_cm;        /* > 0                                             */
+} hb_forward_model_t;
+
+/* Output maps, device pointers, each [n_frames][height][width] float32,
+ * planar.  Any pointer may be NULL to skip that map. */
+typedef struct {
+    float *hb, *hbo2, *thb, *so2;
+} hb_maps_t;
+
+/* Plan-time quantities, for inspection and tests. */
+typedef struct {
+    double E[6];          /* 3x2 row-major Jacobian at the reference point (built on the device, FP64) */
+    double M[6];          /* 2x3 row-major Tikhonov operator (Hb row, HbO2 row), FP64                  */
+    double gamma;         /* absolute gamma = lambda * tr(E'E) / 2                                     */
+    double ref_hb, ref_hbo2;
+    double mu_ref[3];     /* centring offset: -ln of the float32 reference intensities                 */
+    int32_t grid_split;   /* posterior grid split in use                                                */
+    int32_t n_tiles;      /* 8x8-node grid tiles                                                        */
+    int64_t n_nodes;
+} hb_plan_info_t;
+
+/* Fill `desc` with defaults: 64x64, 1 level, FP32, max_batch 1, grid 128x128
+ * over THb [20,200] uM x SO2 [0.3,1], lambda 1e-3, sigma 0.01, floor 1e-4,
+ * reference = grid centre, thb_eps 1e-3, Bayesian low-pass, automatic split. */
+hb_status_t hb_plan_desc_default(hb_plan_desc_t *desc);
+
+/* Validate `desc` and allocate the plan on `device` (hipMalloc happens here
+ * and in hb_set_forward_model only).  On failure *out is set to NULL. */
+hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *out);
+
+/* Set the forward model: builds E and M on the device (FP64, the only double-
+ * precision device code), the centred posterior grid table on the host (FP64
+ * rounded to FP32), and uploads it.  Synchronous.  HB_ERR_ILL_POSED if
+ * E'E + gamma I is singular.  May be called again to replace the model. */
+hb_status_t hb_set_forward_model(hb_plan_t plan, const hb_forward_model_t *fm);
+
+/* Estimate n_frames frames.  d_frames: device, [n][height][width][3] of the
+ * plan's dtype (HWC interleaved R,G,B).  d_out: host struct of device map
+ * pointers.  Asynchronous on `stream`; it neither allocates nor synchronises,
+ * so it may be captured into a HIP graph.  n_frames == 0 is a no-op. */
+hb_status_t hb_estimate_frames(hb_plan_t plan, const void *d_frames, int32_t n_frames,
+                               const hb_maps_t *d_out, void *stream);
+
+/* Synchronise the device and free the plan.  NULL is accepted. */
+hb_status_t hb_destroy(hb_plan_t plan);
+
+/* Static description of a status code (never NULL). */
+const char *hb_status_string(hb_status_t status);
+
+/* Device bytes the plan holds (tables + scratch for max_batch), 0 for NULL. */
+size_t hb_plan_device_bytes(hb_plan_t plan);
+
+/* Copy out the plan-time quantities.  HB_ERR_NO_FORWARD_MODEL before the
+ * model is set. */
+hb_status_t hb_plan_get_info(hb_plan_t plan, hb_plan_info_t *info);
+
+/* Per-kernel timing: when enabled, hb_estimate_frames records HIP events
+ * around each of its kernels on its stream (up to 4096 calls are kept).
+ * hb_plan_get_timing waits for the recorded events, returns the summed
+ * milliseconds and launch counts of the four stages
+ *   [0] log + Haar + Tikhonov, [1] posterior, [2] recomposition + maps,
+ *   [3] whole call,
+ * and clears the record. */
+hb_status_t hb_plan_set_timing(hb_plan_t plan, int32_t enable);
+hb_status_t hb_plan_get_timing(hb_plan_t plan, double ms[4], int64_t launches[4]);
+
+/* Intermediate buffers of the last hb_estimate_frames call, for step-by-step
+ * checks.  Synchronises the device, then copies `bytes` from the start of the
+ * selected buffer of frame `frame` into host memory:
+ *   HB_DEBUG_LOWPASS_OBS: float32 [3][LL], centred low-pass observation
+ *       z_k = ybar_k - mu_ref_k (ybar = block mean of log-attenuation),
+ *       LL = (height >> levels) * (width >> levels), row-major blocks;
+ *   HB_DEBUG_DETAILS: float32 [height][width][2], Tikhonov-inverted
+ *       directional coefficients (Hb, HbO2) in the in-place Haar layout: the
+ *       level-l coefficients of the 2^l block at (r, c) sit at (r, c + h)
+ *       (column difference), (r + h, c) (row difference), (r + h, c + h)
+ *       (diagonal) with h = 2^(l-1); the block's own corner holds 0;
+ *   HB_DEBUG_LOWPASS_EST: float32 [LL][2], low-pass estimate (Hb, HbO2)
+ *       per block (the block mean of the output maps). */
+typedef enum { HB_DEBUG_LOWPASS_OBS = 0, HB_DEBUG_DETAILS = 1, HB_DEBUG_LOWPASS_EST = 2 } hb_debug_buffer_t;
+hb_status_t hb_debug_copy(hb_plan_t plan, int32_t which, int32_t frame, void *host_dst, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HB_H */

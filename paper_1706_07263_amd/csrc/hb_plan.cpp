@@ -1,0 +1,554 @@
+// Host side of the C ABI: plan validation, device buffers, the FP64 posterior
+// grid table and the launch sequence of hb_estimate_frames.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "hb.h"
+#include "hb_internal.h"
+
+using namespace hb;
+
+namespace {
+
+constexpr int kMaxLevels = 5;
+constexpr int kMaxGrid = 4096;
+constexpr int kMaxTimedCalls = 4096;
+
+}  // namespace
+
+struct hb_plan_s {
+    hb_plan_desc_t desc{};
+    int device = 0;
+    Dims dims{};
+    int split = 1;
+    int n_tiles = 0;
+    long long n_nodes = 0;
+    bool has_model = false;
+
+    // Device memory.
+    double *d_k0 = nullptr;   // K0 inputs followed by outputs
+    size_t k0_in = 0;         // doubles of K0 input
+    float *d_mf = nullptr;    // FP32 M (6) + low-pass Tikhonov offset (2)
+    float *d_tiles = nullptr;
+    float *d_z = nullptr;
+    float2 *d_det = nullptr;
+    float *d_part = nullptr;
+    float2 *d_est = nullptr;
+    size_t bytes = 0;
+
+    hb_plan_info_t info{};
+    float iref[3] = {1, 1, 1};
+    float scale = 1.0f;
+
+    bool timing = false;
+    std::vector<hipEvent_t> events;  // 4 per recorded call
+    int timed_calls = 0;
+    int last_frames = 0;
+};
+
+namespace {
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+hb_status_t check_desc(const hb_plan_desc_t *d) {
+    if (!d) return HB_ERR_INVALID_ARG;
+    if (d->levels < 0 || d->levels > kMaxLevels) return HB_ERR_INVALID_ARG;
+    if (d->width <= 0 || d->height <= 0) return HB_ERR_SHAPE;
+    if ((d->width % (1 << d->levels)) != 0 || (d->height % (1 << d->levels)) != 0) return HB_ERR_SHAPE;
+    if ((long long)d->width * d->height > (1LL << 28)) return HB_ERR_SHAPE;
+    if (d->frame_dtype != HB_F32 && d->frame_dtype != HB_F16 && d->frame_dtype != HB_BF16)
+        return HB_ERR_INVALID_ARG;
+    if (d->max_batch < 1 || d->max_batch > 4096) return HB_ERR_INVALID_ARG;
+    if (d->grid_thb < 1 || d->grid_so2 < 1 || d->grid_thb > kMaxGrid || d->grid_so2 > kMaxGrid)
+        return HB_ERR_INVALID_ARG;
+    if (!is_finite(d->thb_min) || !is_finite(d->thb_max) || d->thb_min < 0 || d->thb_max < d->thb_min)
+        return HB_ERR_INVALID_ARG;
+    if (!is_finite(d->so2_min) || !is_finite(d->so2_max) || d->so2_min < 0 || d->so2_max > 1 ||
+        d->so2_max < d->so2_min)
+        return HB_ERR_INVALID_ARG;
+    if (!is_finite(d->lambda) || d->lambda < 0) return HB_ERR_INVALID_ARG;
+    if (!is_finite(d->sigma) || !(d->sigma > 0)) return HB_ERR_INVALID_ARG;
+    if (!is_finite(d->intensity_floor) || !(d->intensity_floor > 0)) return HB_ERR_INVALID_ARG;
+    if (!is_finite(d->thb_eps)) return HB_ERR_INVALID_ARG;
+    const bool ref_default = std::isnan(d->ref_thb) && std::isnan(d->ref_so2);
+    if (!ref_default && (!is_finite(d->ref_thb) || !is_finite(d->ref_so2) || d->ref_thb < 0 ||
+                         d->ref_so2 < 0 || d->ref_so2 > 1))
+        return HB_ERR_INVALID_ARG;
+    if (d->lowpass != HB_LOWPASS_BAYES && d->lowpass != HB_LOWPASS_TIKHONOV) return HB_ERR_INVALID_ARG;
+    if (d->grid_split < 0 || d->grid_split > 256) return HB_ERR_INVALID_ARG;
+    return HB_OK;
+}
+
+Dims make_dims(const hb_plan_desc_t &d) {
+    Dims m{};
+    m.H = d.height;
+    m.W = d.width;
+    m.levels = d.levels;
+    m.hl = d.height >> d.levels;
+    m.wl = d.width >> d.levels;
+    m.LL = (long long)m.hl * m.wl;
+    m.bps = std::max(1, kStripPixels >> (2 * d.levels));
+    m.strips_per_row = (m.wl + m.bps - 1) / m.bps;
+    return m;
+}
+
+int auto_split(const Dims &dm, int n_tiles) {
+    // Aim for about four waves per SIMD (1024 SIMDs) from a single frame.
+    const long long lanes = (dm.LL + kPosteriorPix - 1) / kPosteriorPix;
+    const long long waves = std::max(1LL, (lanes + 63) / 64);
+    int s = 1;
+    while (s < 64 && waves * s < 4096) s *= 2;
+    return std::max(1, std::min(s, n_tiles));
+}
+
+hb_status_t dev_alloc(hb_plan_s *p, void **ptr, size_t bytes) {
+    if (hipMalloc(ptr, bytes) != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return HB_ERR_OUT_OF_MEMORY;
+    }
+    p->bytes += bytes;
+    return HB_OK;
+}
+
+void free_plan(hb_plan_s *p) {
+    (void)hipFree(p->d_k0);
+    (void)hipFree(p->d_mf);
+    (void)hipFree(p->d_tiles);
+    (void)hipFree(p->d_z);
+    (void)hipFree(p->d_det);
+    (void)hipFree(p->d_part);
+    (void)hipFree(p->d_est);
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+    delete p;
+}
+
+hb_status_t set_device(int dev) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return HB_ERR_DEVICE;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return HB_ERR_DEVICE;
+    return HB_OK;
+}
+
+double lin(double lo, double hi, int n, int i) { return n == 1 ? lo : lo + (hi - lo) * (double)i / (double)(n - 1); }
+
+// RGB log-attenuation of concentration (hb, hbo2): channel k integrates
+// Beer-Lambert attenuation over its normalised sensitivity.
+struct ForwardModel {
+    int n = 0;
+    std::vector<double> ehb, eox, resp;  // resp rows normalised
+    double L = 0;
+    void mu(double hb, double hbo2, double out[3]) const {
+        for (int k = 0; k < 3; ++k) {
+            double acc = 0.0;
+            for (int j = 0; j < n; ++j) acc += resp[k * n + j] * std::exp(-L * (ehb[j] * hb + eox[j] * hbo2));
+            out[k] = -std::log(acc);
+        }
+    }
+};
+
+// Build the tiled, centred, scaled grid table (FP64 arithmetic, FP32 storage).
+void build_tiles(const hb_plan_desc_t &d, const ForwardModel &fm, const double mu_ref[3], double scale,
+                 std::vector<float> &tiles) {
+    const int GT = d.grid_thb, GS = d.grid_so2;
+    const int nta = (GT + kTileSide - 1) / kTileSide, nts = (GS + kTileSide - 1) / kTileSide;
+    const int n_tiles = nta * nts;
+    tiles.assign((size_t)n_tiles * kTileFloats, 0.0f);
+    auto work = [&](int t_begin, int t_end) {
+        for (int t = t_begin; t < t_end; ++t) {
+            const int ta = t / nts, ts = t % nts;
+            const int a0 = ta * kTileSide, b0 = ts * kTileSide;
+            const int na = std::min(kTileSide, GT - a0), nb = std::min(kTileSide, GS - b0);
+            float *T = &tiles[(size_t)t * kTileFloats];
+            float *N = T + kTileHdr;
+            double chb[kTileNodes], cox[kTileNodes];
+            double mhb = 0, mox = 0;
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    const double thb = lin(d.thb_min, d.thb_max, GT, a0 + i);
+                    const double so2 = lin(d.so2_min, d.so2_max, GS, b0 + j);
+                    const int slot = i * kTileSide + j;
+                    chb[slot] = thb * (1.0 - so2);
+                    cox[slot] = thb * so2;
+                    mhb += chb[slot];
+                    mox += cox[slot];
+                }
+            const float centre_hb = (float)(mhb / (na * nb)), centre_ox = (float)(mox / (na * nb));
+            float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int slot = 0; slot < kTileNodes; ++slot) {
+                const int i = slot / kTileSide, j = slot % kTileSide;
+                if (i >= na || j >= nb) {
+                    for (int k = 0; k < 3; ++k) N[k * kTileNodes + slot] = kPadCoord;
+                    N[3 * kTileNodes + slot] = 0.0f;
+                    N[4 * kTileNodes + slot] = 0.0f;
+                    continue;
+                }
+                double m[3];
+                fm.mu(chb[slot], cox[slot], m);
+                for (int k = 0; k < 3; ++k) {
+                    const float v = (float)(scale * (m[k] - mu_ref[k]));
+                    N[k * kTileNodes + slot] = v;
+                    lo[k] = std::min(lo[k], v);
+                    hi[k] = std::max(hi[k], v);
+                }
+                N[3 * kTileNodes + slot] = (float)(chb[slot] - (double)centre_hb);
+                N[4 * kTileNodes + slot] = (float)(cox[slot] - (double)centre_ox);
+            }
+            T[0] = centre_hb;
+            T[1] = centre_ox;
+            for (int k = 0; k < 3; ++k) {
+                T[2 + k] = lo[k];
+                T[5 + k] = hi[k];
+            }
+            const int probe = ((na - 1) / 2) * kTileSide + (nb - 1) / 2;
+            std::memcpy(&T[8], &probe, sizeof(int));
+        }
+    };
+    unsigned nt = std::max(1u, std::min(std::thread::hardware_concurrency(), 32u));
+    nt = std::min<unsigned>(nt, (unsigned)n_tiles);
+    std::vector<std::thread> th;
+    for (unsigned i = 0; i < nt; ++i)
+        th.emplace_back(work, (int)((long long)n_tiles * i / nt), (int)((long long)n_tiles * (i + 1) / nt));
+    for (auto &x : th) x.join();
+}
+
+}  // namespace
+
+extern "C" {
+
+hb_status_t hb_plan_desc_default(hb_plan_desc_t *d) {
+    if (!d) return HB_ERR_INVALID_ARG;
+    std::memset(d, 0, sizeof(*d));
+    d->width = 64;
+    d->height = 64;
+    d->levels = 1;
+    d->frame_dtype = HB_F32;
+    d->max_batch = 1;
+    d->grid_thb = 128;
+    d->grid_so2 = 128;
+    d->thb_min = 20.0;
+    d->thb_max = 200.0;
+    d->so2_min = 0.3;
+    d->so2_max = 1.0;
+    d->lambda = 1e-3;
+    d->sigma = 0.01;
+    d->intensity_floor = 1e-4;
+    d->ref_thb = NAN;
+    d->ref_so2 = NAN;
+    d->thb_eps = 1e-3;
+    d->lowpass = HB_LOWPASS_BAYES;
+    d->grid_split = 0;
+    return HB_OK;
+}
+
+const char *hb_status_string(hb_status_t s) {
+    switch (s) {
+        case HB_OK: return "ok";
+        case HB_ERR_INVALID_ARG: return "invalid argument";
+        case HB_ERR_SHAPE: return "invalid frame shape (width and height must be positive multiples of 2^levels)";
+        case HB_ERR_NO_FORWARD_MODEL: return "forward model not set";
+        case HB_ERR_OUT_OF_MEMORY: return "device allocation failed";
+        case HB_ERR_DEVICE: return "HIP device error";
+        case HB_ERR_ILL_POSED: return "Tikhonov system is singular";
+        case HB_ERR_BATCH: return "n_frames exceeds the plan's max_batch";
+    }
+    return "unknown status";
+}
+
+hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *out) {
+    if (!out) return HB_ERR_INVALID_ARG;
+    *out = nullptr;
+    hb_status_t st = check_desc(desc);
+    if (st != HB_OK) return st;
+    if (device < 0) return HB_ERR_INVALID_ARG;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+        (void)hipGetLastError();
+        return HB_ERR_DEVICE;
+    }
+    if (set_device(device) != HB_OK) return HB_ERR_DEVICE;
+
+    hb_plan_s *p = new (std::nothrow) hb_plan_s();
+    if (!p) return HB_ERR_OUT_OF_MEMORY;
+    p->desc = *desc;
+    p->device = device;
+    p->dims = make_dims(*desc);
+    const int nta = (desc->grid_thb + kTileSide - 1) / kTileSide, nts = (desc->grid_so2 + kTileSide - 1) / kTileSide;
+    p->n_tiles = nta * nts;
+    p->n_nodes = (long long)desc->grid_thb * desc->grid_so2;
+    p->split = desc->grid_split > 0 ? std::min(desc->grid_split, p->n_tiles) : auto_split(p->dims, p->n_tiles);
+
+    const size_t nb = (size_t)desc->max_batch;
+    const size_t LL = (size_t)p->dims.LL;
+    const size_t HW = (size_t)desc->height * desc->width;
+    st = HB_OK;
+    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_mf, sizeof(float) * 8);
+    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_tiles, sizeof(float) * (size_t)p->n_tiles * kTileFloats);
+    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_z, sizeof(float) * nb * 3 * LL);
+    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_det, sizeof(float2) * nb * HW);
+    if (st == HB_OK && desc->lowpass == HB_LOWPASS_BAYES)
+        st = dev_alloc(p, (void **)&p->d_part, sizeof(float) * nb * p->split * kPartFields * LL);
+    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_est, sizeof(float2) * nb * LL);
+    if (st != HB_OK) {
+        free_plan(p);
+        return st;
+    }
+    p->info.grid_split = p->split;
+    p->info.n_tiles = p->n_tiles;
+    p->info.n_nodes = p->n_nodes;
+    *out = p;
+    return HB_OK;
+}
+
+hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
+    if (!p || !fm) return HB_ERR_INVALID_ARG;
+    const int n = fm->n_wavelengths;
+    if (n < 1 || n > 100000 || !fm->eps_hb || !fm->eps_hbo2 || !fm->response) return HB_ERR_INVALID_ARG;
+    if (!is_finite(fm->path_length_cm) || !(fm->path_length_cm > 0)) return HB_ERR_INVALID_ARG;
+    ForwardModel model;
+    model.n = n;
+    model.L = fm->path_length_cm;
+    model.ehb.assign(fm->eps_hb, fm->eps_hb + n);
+    model.eox.assign(fm->eps_hbo2, fm->eps_hbo2 + n);
+    model.resp.assign(fm->response, fm->response + 3 * (size_t)n);
+    for (int j = 0; j < n; ++j)
+        if (!is_finite(model.ehb[j]) || !is_finite(model.eox[j])) return HB_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k) {
+        double sum = 0;
+        for (int j = 0; j < n; ++j) {
+            const double v = model.resp[k * n + j];
+            if (!is_finite(v) || v < 0) return HB_ERR_INVALID_ARG;
+            sum += v;
+        }
+        if (!(sum > 0)) return HB_ERR_INVALID_ARG;
+        for (int j = 0; j < n; ++j) model.resp[k * n + j] /= sum;
+    }
+    if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
+
+    const hb_plan_desc_t &d = p->desc;
+    double ref_thb = d.ref_thb, ref_so2 = d.ref_so2;
+    if (std::isnan(ref_thb) && std::isnan(ref_so2)) {
+        ref_thb = 0.5 * (d.thb_min + d.thb_max);
+        ref_so2 = 0.5 * (d.so2_min + d.so2_max);
+    }
+    const double ref_hb = ref_thb * (1.0 - ref_so2), ref_hbo2 = ref_thb * ref_so2;
+
+    // K0 (device, FP64): E and M.
+    std::vector<double> in(5 + 5 * (size_t)n);
+    in[0] = n;
+    in[1] = model.L;
+    in[2] = ref_hb;
+    in[3] = ref_hbo2;
+    in[4] = d.lambda;
+    std::copy(model.ehb.begin(), model.ehb.end(), in.begin() + 5);
+    std::copy(model.eox.begin(), model.eox.end(), in.begin() + 5 + n);
+    std::copy(model.resp.begin(), model.resp.end(), in.begin() + 5 + 2 * n);
+    if (p->d_k0 && p->k0_in < in.size()) {
+        (void)hipFree(p->d_k0);
+        p->d_k0 = nullptr;
+    }
+    if (!p->d_k0) {
+        if (dev_alloc(p, (void **)&p->d_k0, sizeof(double) * (in.size() + 16)) != HB_OK) return HB_ERR_OUT_OF_MEMORY;
+        p->k0_in = in.size();
+    }
+    double k0_out[14];
+    if (hipMemcpy(p->d_k0, in.data(), sizeof(double) * in.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return HB_ERR_DEVICE;
+    if (launch_tikhonov_fp64(p->d_k0, p->d_k0 + p->k0_in, p->d_mf, nullptr) != hipSuccess) return HB_ERR_DEVICE;
+    if (hipMemcpy(k0_out, p->d_k0 + p->k0_in, sizeof(k0_out), hipMemcpyDeviceToHost) != hipSuccess)
+        return HB_ERR_DEVICE;
+    if (k0_out[13] != 1.0) return HB_ERR_ILL_POSED;
+
+    // Centring: float32 reference intensities and the exact offsets they imply.
+    double mu_ref[3];
+    model.mu(ref_hb, ref_hbo2, mu_ref);
+    double r[3];
+    for (int k = 0; k < 3; ++k) {
+        p->iref[k] = (float)std::exp(-mu_ref[k]);
+        r[k] = -std::log((double)p->iref[k]);
+    }
+    p->scale = (float)std::sqrt(1.4426950408889634 / (2.0 * d.sigma * d.sigma));
+
+    // Low-pass Tikhonov offset: c_ref + M (r - mu_ref), so that the low-pass
+    // estimate is that offset + M z with z = ybar - r.
+    float mf_extra[2];
+    for (int i = 0; i < 2; ++i) {
+        double v = (i == 0 ? ref_hb : ref_hbo2);
+        for (int k = 0; k < 3; ++k) v += k0_out[6 + 3 * i + k] * (r[k] - mu_ref[k]);
+        mf_extra[i] = (float)v;
+    }
+    if (hipMemcpy(p->d_mf + 6, mf_extra, sizeof(mf_extra), hipMemcpyHostToDevice) != hipSuccess)
+        return HB_ERR_DEVICE;
+
+    std::vector<float> tiles;
+    build_tiles(d, model, r, (double)p->scale, tiles);
+    if (hipMemcpy(p->d_tiles, tiles.data(), sizeof(float) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return HB_ERR_DEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return HB_ERR_DEVICE;
+
+    for (int i = 0; i < 6; ++i) {
+        p->info.E[i] = k0_out[i];
+        p->info.M[i] = k0_out[6 + i];
+    }
+    p->info.gamma = k0_out[12];
+    p->info.ref_hb = ref_hb;
+    p->info.ref_hbo2 = ref_hbo2;
+    for (int k = 0; k < 3; ++k) p->info.mu_ref[k] = r[k];
+    p->has_model = true;
+    return HB_OK;
+}
+
+hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_frames, const hb_maps_t *d_out,
+                               void *stream) {
+    if (!p || !d_out) return HB_ERR_INVALID_ARG;
+    if (n_frames < 0) return HB_ERR_INVALID_ARG;
+    if (n_frames > p->desc.max_batch) return HB_ERR_BATCH;
+    if (!p->has_model) return HB_ERR_NO_FORWARD_MODEL;
+    if (n_frames == 0) return HB_OK;
+    if (!d_frames) return HB_ERR_INVALID_ARG;
+    if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+
+    hipEvent_t *ev = nullptr;
+    if (p->timing && p->timed_calls < kMaxTimedCalls) {
+        const size_t need = 4 * (size_t)(p->timed_calls + 1);
+        while (p->events.size() < need) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return HB_ERR_DEVICE;
+            p->events.push_back(e);
+        }
+        ev = &p->events[4 * (size_t)p->timed_calls];
+        p->timed_calls++;
+    }
+    auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
+
+    HaarArgs ha{};
+    ha.d = p->dims;
+    ha.dtype = p->desc.frame_dtype;
+    ha.floor = (float)p->desc.intensity_floor;
+    for (int k = 0; k < 3; ++k) ha.iref[k] = p->iref[k];
+    ha.M = p->d_mf;
+    ha.z = p->d_z;
+    ha.det = p->d_det;
+
+    if (mark(0) != hipSuccess) return HB_ERR_DEVICE;
+    if (launch_log_haar(d_frames, n_frames, ha, s) != hipSuccess) return HB_ERR_DEVICE;
+    if (mark(1) != hipSuccess) return HB_ERR_DEVICE;
+    if (p->desc.lowpass == HB_LOWPASS_BAYES) {
+        PosteriorArgs pa{};
+        pa.LL = p->dims.LL;
+        pa.n_frames = n_frames;
+        pa.z = p->d_z;
+        pa.tiles = p->d_tiles;
+        pa.n_tiles = p->n_tiles;
+        pa.split = p->split;
+        pa.scale = p->scale;
+        pa.part = p->d_part;
+        if (launch_posterior(pa, s) != hipSuccess) return HB_ERR_DEVICE;
+    }
+    if (mark(2) != hipSuccess) return HB_ERR_DEVICE;
+    RecomposeArgs ra{};
+    ra.d = p->dims;
+    ra.lowpass = p->desc.lowpass;
+    ra.split = p->split;
+    ra.part = p->d_part;
+    ra.z = p->d_z;
+    ra.M = p->d_mf;
+    ra.det = p->d_det;
+    ra.est = p->d_est;
+    ra.thb_eps = (float)p->desc.thb_eps;
+    ra.hb = d_out->hb;
+    ra.hbo2 = d_out->hbo2;
+    ra.thb = d_out->thb;
+    ra.so2 = d_out->so2;
+    if (launch_recompose(n_frames, ra, s) != hipSuccess) return HB_ERR_DEVICE;
+    if (mark(3) != hipSuccess) return HB_ERR_DEVICE;
+    p->last_frames = n_frames;
+    return HB_OK;
+}
+
+hb_status_t hb_destroy(hb_plan_t p) {
+    if (!p) return HB_OK;
+    hb_status_t st = HB_OK;
+    if (set_device(p->device) != HB_OK || hipDeviceSynchronize() != hipSuccess) st = HB_ERR_DEVICE;
+    free_plan(p);
+    return st;
+}
+
+size_t hb_plan_device_bytes(hb_plan_t p) { return p ? p->bytes : 0; }
+
+hb_status_t hb_plan_get_info(hb_plan_t p, hb_plan_info_t *info) {
+    if (!p || !info) return HB_ERR_INVALID_ARG;
+    if (!p->has_model) return HB_ERR_NO_FORWARD_MODEL;
+    *info = p->info;
+    return HB_OK;
+}
+
+hb_status_t hb_plan_set_timing(hb_plan_t p, int32_t enable) {
+    if (!p) return HB_ERR_INVALID_ARG;
+    p->timing = enable != 0;
+    p->timed_calls = 0;
+    return HB_OK;
+}
+
+hb_status_t hb_plan_get_timing(hb_plan_t p, double ms[4], int64_t launches[4]) {
+    if (!p || !ms || !launches) return HB_ERR_INVALID_ARG;
+    for (int i = 0; i < 4; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
+    for (int c = 0; c < p->timed_calls; ++c) {
+        hipEvent_t *e = &p->events[4 * (size_t)c];
+        if (hipEventSynchronize(e[3]) != hipSuccess) return HB_ERR_DEVICE;
+        const int from[4] = {0, 1, 2, 0}, to[4] = {1, 2, 3, 3};
+        for (int i = 0; i < 4; ++i) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, e[from[i]], e[to[i]]) != hipSuccess) return HB_ERR_DEVICE;
+            ms[i] += t;
+        }
+        launches[0]++;
+        if (p->desc.lowpass == HB_LOWPASS_BAYES) launches[1]++;
+        launches[2]++;
+        launches[3]++;
+    }
+    p->timed_calls = 0;
+    return HB_OK;
+}
+
+hb_status_t hb_debug_copy(hb_plan_t p, int32_t which, int32_t frame, void *host_dst, size_t bytes) {
+    if (!p || !host_dst) return HB_ERR_INVALID_ARG;
+    if (frame < 0 || frame >= p->desc.max_batch) return HB_ERR_INVALID_ARG;
+    const size_t LL = (size_t)p->dims.LL, HW = (size_t)p->desc.width * p->desc.height;
+    const void *src = nullptr;
+    size_t avail = 0;
+    switch (which) {
+        case HB_DEBUG_LOWPASS_OBS:
+            src = p->d_z + (size_t)frame * 3 * LL;
+            avail = sizeof(float) * 3 * LL;
+            break;
+        case HB_DEBUG_DETAILS:
+            src = p->d_det + (size_t)frame * HW;
+            avail = sizeof(float2) * HW;
+            break;
+        case HB_DEBUG_LOWPASS_EST:
+            src = p->d_est + (size_t)frame * LL;
+            avail = sizeof(float2) * LL;
+            break;
+        default:
+            return HB_ERR_INVALID_ARG;
+    }
+    if (bytes > avail) return HB_ERR_INVALID_ARG;
+    if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return HB_ERR_DEVICE;
+    if (hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost) != hipSuccess) return HB_ERR_DEVICE;
+    return HB_OK;
+}
+
+}  // extern "C"

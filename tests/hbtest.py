@@ -1,0 +1,148 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C ABI and
+the FP64 oracle on the same seeded inputs."""
+from __future__ import annotations
+
+import math
+import os
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from oracle import hb_oracle as orc
+from paper_1706_07263_amd import synth
+
+# FP32-mode tolerances (uM; SO2 relative to THb), stated for this path.
+TOL_HB = 1e-4
+TOL_THB = 2e-4
+TOL_SO2_NUM = 3e-4     # |dSO2| <= TOL_SO2_NUM / THb where THb >= 1 uM
+
+
+def oracle_model(sp: synth.Spectra) -> orc.Model:
+    return orc.Model(sp.eps_hb, sp.eps_hbo2, sp.response, sp.path_length_cm)
+
+
+def oracle_params(width: int, height: int, settings: Dict[str, object], lowpass: int = 0,
+                  ref: Optional[Tuple[float, float]] = None) -> orc.Params:
+    p = orc.Params(width=width, height=height, levels=int(settings["levels"]),
+                   grid_thb=int(settings["grid_thb"]), grid_so2=int(settings["grid_so2"]),
+                   thb_min=float(settings["thb_min"]), thb_max=float(settings["thb_max"]),
+                   so2_min=float(settings["so2_min"]), so2_max=float(settings["so2_max"]),
+                   lambda_rel=float(settings["lam"]), sigma=float(settings["sigma"]),
+                   lowpass=lowpass)
+    if ref is not None:
+        p.ref_hb, p.ref_hbo2 = ref
+    return p
+
+
+def run_oracle(frames: np.ndarray, dtype: str, settings, lowpass: int = 0,
+               sp: Optional[synth.Spectra] = None) -> np.ndarray:
+    """frames [n][H][W][3] storage dtype -> maps [n][4][H][W] float64."""
+    sp = sp or synth.spectra()
+    n, h, w, _ = frames.shape
+    f64 = synth.storage_to_f64(frames, dtype)
+    return orc.estimate(oracle_params(w, h, settings, lowpass), oracle_model(sp), f64)
+
+
+def to_device(frames: np.ndarray, dtype: str):
+    import torch
+    if dtype == "bf16":
+        t = torch.from_numpy(frames.view(np.int16).copy())
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(frames))
+    return t.cuda()
+
+
+class GpuRun:
+    """One plan on cuda:0, reused across calls with the same shape."""
+
+    def __init__(self, width: int, height: int, settings, dtype: str = "f32", max_batch: int = 1,
+                 lowpass: int = 0, grid_split: int = 0, sp: Optional[synth.Spectra] = None):
+        import torch
+        from paper_1706_07263_amd import hb
+        self.hb = hb
+        self.torch = torch
+        self.desc = hb.make_desc(width, height, levels=int(settings["levels"]), dtype=dtype,
+                                 max_batch=max_batch, grid_thb=int(settings["grid_thb"]),
+                                 grid_so2=int(settings["grid_so2"]),
+                                 thb_min=float(settings["thb_min"]), thb_max=float(settings["thb_max"]),
+                                 so2_min=float(settings["so2_min"]), so2_max=float(settings["so2_max"]),
+                                 lam=float(settings["lam"]), sigma=float(settings["sigma"]),
+                                 lowpass=lowpass, grid_split=grid_split)
+        self.plan = hb.Plan(self.desc, 0)
+        self.plan.set_forward_model(sp or synth.spectra())
+        self.dtype = dtype
+        self.h, self.w = height, width
+
+    def __call__(self, frames: np.ndarray, which: Sequence[bool] = (True, True, True, True)) -> np.ndarray:
+        torch = self.torch
+        n = frames.shape[0]
+        d = to_device(frames, self.dtype)
+        maps = [torch.full((n, self.h, self.w), float("nan"), device="cuda", dtype=torch.float32) if k else None
+                for k in which]
+        self.plan.estimate(d, maps)
+        torch.cuda.synchronize()
+        out = np.full((n, 4, self.h, self.w), np.nan, dtype=np.float32)
+        for i, m in enumerate(maps):
+            if m is not None:
+                out[:, i] = m.cpu().numpy()
+        return out
+
+    def debug(self, which: int, frame: int = 0) -> np.ndarray:
+        hb = self.hb
+        LL = (self.h >> self.desc.levels) * (self.w >> self.desc.levels)
+        if which == hb.HB_DEBUG_LOWPASS_OBS:
+            out = np.zeros((3, LL), np.float32)
+        elif which == hb.HB_DEBUG_DETAILS:
+            out = np.zeros((self.h, self.w, 2), np.float32)
+        else:
+            out = np.zeros((LL, 2), np.float32)
+        return hb.hb_debug_copy(self.plan.handle, which, frame, out)
+
+    def close(self):
+        self.plan.close()
+
+
+def assert_maps_close(gpu: np.ndarray, ora: np.ndarray, where: str = "") -> Dict[str, float]:
+    """gpu [n][4][H][W] float32 vs oracle float64 at the stated tolerances.
+    NaN must coincide.  Returns the max errors."""
+    g = gpu.astype(np.float64)
+    o = ora
+    nan_g, nan_o = np.isnan(g), np.isnan(o)
+    assert np.array_equal(nan_g[:, :3], nan_o[:, :3]), f"{where}: NaN pattern differs"
+    fin = ~nan_o
+    err = {}
+    for i, (name, tol) in enumerate((("hb", TOL_HB), ("hbo2", TOL_HB), ("thb", TOL_THB))):
+        e = np.abs(g[:, i] - o[:, i])[fin[:, i]]
+        err[name] = float(e.max()) if e.size else 0.0
+        assert err[name] <= tol, f"{where}: max |d{name}| = {err[name]:.3e} > {tol:.1e}"
+    thb = o[:, 2]
+    sel = fin[:, 3] & (thb >= 1.0)
+    e = np.abs(g[:, 3] - o[:, 3])[sel] * thb[sel]
+    err["so2_x_thb"] = float(e.max()) if e.size else 0.0
+    assert err["so2_x_thb"] <= TOL_SO2_NUM, f"{where}: max |dSO2|*THb = {err['so2_x_thb']:.3e}"
+    return err
+
+
+def crops(h: int, w: int, levels: int, size: int, count: int, seed: int) -> List[Tuple[int, int, int, int]]:
+    """Aligned crops (r0, c0, hh, ww): the four corners plus random interior ones."""
+    b = 1 << levels
+    size = max(b, (size // b) * b)
+    rng = np.random.default_rng(seed)
+    out = [(0, 0), (0, w - size), (h - size, 0), (h - size, w - size)]
+    for _ in range(max(0, count - 4)):
+        out.append((int(rng.integers(0, (h - size) // b + 1)) * b, int(rng.integers(0, (w - size) // b + 1)) * b))
+    return [(r, c, size, size) for r, c in out]
+
+
+def sampled_parity(gpu_maps: np.ndarray, frames: np.ndarray, dtype: str, settings, crop_list,
+                   lowpass: int = 0, where: str = "") -> Dict[str, float]:
+    """Compare full-frame GPU maps with the oracle evaluated on aligned crops
+    (blocks are independent, so a crop reproduces the full-frame values)."""
+    worst: Dict[str, float] = {}
+    for (r, c, hh, ww) in crop_list:
+        sub = np.ascontiguousarray(frames[:, r:r + hh, c:c + ww])
+        ora = run_oracle(sub, dtype, settings, lowpass)
+        e = assert_maps_close(gpu_maps[:, :, r:r + hh, c:c + ww], ora, f"{where} crop {(r, c)}")
+        for k, v in e.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    return worst

@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, on
+seeded inputs small enough for the oracle to run in full."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import hb_oracle as orc
+from paper_1706_07263_amd import synth
+from tests import hbtest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _settings(levels=1, grid=32, **kw):
+    s = synth.plan_settings(levels=levels, grid=grid)
+    s.update(kw)
+    return s
+
+
+def test_config1_full_frame(torch_cuda):
+    w = synth.config1()
+    run = hbtest.GpuRun(64, 64, w.plan)
+    gpu = run(w.frames)
+    ora = hbtest.run_oracle(w.frames, "f32", w.plan)
+    err = hbtest.assert_maps_close(gpu, ora, "config1")
+    print("config1 errors", err)
+    run.close()
+
+
+def test_steps_match_oracle(torch_cuda):
+    """Each step on its own: FP64 Tikhonov operator (K0), the centred low-pass
+    observation and the Tikhonov details (K1), the low-pass estimate (K2+K3)."""
+    sp = synth.spectra()
+    w = synth.config1()
+    s = w.plan
+    run = hbtest.GpuRun(64, 64, s)
+    run(w.frames)
+    info = run.plan.info()
+    model = hbtest.oracle_model(sp)
+    p = hbtest.oracle_params(64, 64, s)
+    E = orc.jacobian(model, *p.ref())
+    M, gamma = orc.tikhonov(E, s["lam"])
+    assert np.allclose(info["E"], E, rtol=1e-12, atol=0)
+    assert np.allclose(info["M"], M, rtol=1e-11, atol=0)
+    assert info["gamma"] == pytest.approx(gamma, rel=1e-12)
+    # low-pass observation: ybar - mu_ref per block
+    y = -np.log(np.maximum(w.frames[0].astype(np.float64), 1e-4))
+    ybar = y.reshape(32, 2, 32, 2, 3).mean(axis=(1, 3)).reshape(-1, 3)
+    z = run.debug(run.hb.HB_DEBUG_LOWPASS_OBS).T
+    assert np.max(np.abs(z - (ybar - info["mu_ref"]))) < 2e-7
+    # Tikhonov details in the in-place layout vs the oracle's Mallat layout
+    det = run.debug(run.hb.HB_DEBUG_DETAILS)
+    co = np.stack([orc.haar_forward(y[:, :, k], 1) for k in range(3)], axis=-1)
+    dc = co @ M.T   # (Hb, HbO2) per coefficient
+    for (dr, dcc, band) in [(1, 0, "row"), (1, 1, "diag"), (0, 1, "col")]:
+        mal = {"row": dc[32:, :32], "diag": dc[32:, 32:], "col": dc[:32, 32:]}[band]
+        inplace = det[dr::2, dcc::2]
+        assert np.max(np.abs(inplace - mal)) < 2e-5, band
+    assert np.all(det[0::2, 0::2] == 0)
+    # low-pass estimate per block vs the oracle posterior mean
+    est = run.debug(run.hb.HB_DEBUG_LOWPASS_EST)
+    c, mu = orc.grid(p, model)
+    want = np.array([orc.posterior_mean(c, mu, ybar[i], s["sigma"]) for i in range(0, 1024, 37)])
+    assert np.max(np.abs(est[0:1024:37] - want)) < 1e-4
+    run.close()
+
+
+@pytest.mark.parametrize("h,w,levels,grid", [
+    (96, 200, 1, (37, 29)),        # ragged strips, ragged grid tiles
+    (64, 2304, 1, (16, 16)),       # several strips per block row, ragged tail
+    (40, 72, 2, (24, 20)),
+    (32, 96, 3, (20, 12)),
+    (32, 64, 4, (9, 9)),
+    (64, 96, 5, (8, 16)),
+    (8, 3000, 0, (12, 10)),        # posterior on every pixel, several chunks
+])
+def test_shapes_levels_and_ragged_grids(torch_cuda, h, w, levels, grid):
+    fr, _, _ = synth.single_frame(h, w, config=60, stream=levels)
+    s = _settings(levels=levels, grid=grid[0], grid_so2=grid[1])
+    run = hbtest.GpuRun(w, h, s)
+    gpu = run(fr[None])
+    ora = hbtest.run_oracle(fr[None], "f32", s)
+    hbtest.assert_maps_close(gpu, ora, f"{h}x{w} L{levels} G{grid}")
+    run.close()
+
+
+@pytest.mark.parametrize("split", [1, 3, 7, 16])
+def test_grid_split_merge(torch_cuda, split):
+    w = synth.config1()
+    run = hbtest.GpuRun(64, 64, w.plan, grid_split=split)
+    assert run.plan.info()["grid_split"] == split
+    gpu = run(w.frames)
+    hbtest.assert_maps_close(gpu, hbtest.run_oracle(w.frames, "f32", w.plan), f"split {split}")
+    run.close()
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_tikhonov_lowpass_mode(torch_cuda, levels):
+    fr, _, _ = synth.single_frame(64, 96, config=61, stream=levels)
+    s = _settings(levels=levels)
+    run = hbtest.GpuRun(96, 64, s, lowpass=1)
+    gpu = run(fr[None])
+    ora = hbtest.run_oracle(fr[None], "f32", s, lowpass=1)
+    hbtest.assert_maps_close(gpu, ora, f"tikhonov L{levels}")
+    run.close()
+
+
+def test_batch_invariance_and_determinism(torch_cuda):
+    frames = np.stack([synth.single_frame(128, 128, config=62, stream=i)[0] for i in range(3)])
+    s = _settings(levels=2, grid=64)
+    run = hbtest.GpuRun(128, 128, s, max_batch=3)
+    both = run(frames)
+    again = run(frames)
+    assert np.array_equal(both, again, equal_nan=True)
+    alone = run(frames[1:2])
+    assert np.array_equal(alone[0], both[1], equal_nan=True)
+    run.close()
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_half_storage_matches_oracle_on_quantised_input(torch_cuda, dtype):
+    w = synth.config1(dtype)
+    run = hbtest.GpuRun(64, 64, w.plan, dtype=dtype)
+    gpu = run(w.frames)
+    ora = hbtest.run_oracle(w.frames, dtype, w.plan)
+    hbtest.assert_maps_close(gpu, ora, dtype)
+    run.close()
+
+
+def test_degenerate_pixels(torch_cuda):
+    """Dark (clamped), negative, saturated (> 1, negative attenuation), NaN and
+    far-from-model pixels, and a block-constant region."""
+    fr, _, _ = synth.single_frame(64, 64, config=63)
+    fr = fr.copy()
+    fr[0:2, 0:2] = 0.0             # clamps to the floor: far from every node
+    fr[4:6, 8:10, 1] = -0.5
+    fr[10:12, 10:12] = 1.3         # brighter than the source
+    fr[20, 21, 2] = np.nan
+    fr[32:40, 32:40] = fr[32, 32]  # block-constant
+    fr[50:52, 50:52, 0] = 1e-3     # one dark channel
+    s = synth.plan_settings(levels=1, grid=32)
+    run = hbtest.GpuRun(64, 64, s)
+    gpu = run(fr[None])
+    ora = hbtest.run_oracle(fr[None], "f32", s)
+    hbtest.assert_maps_close(gpu, ora, "degenerate")
+    assert np.all(np.isnan(gpu[0, :, 20:22, 20:22]))
+    run.close()
+
+
+def test_small_sigma_and_single_node(torch_cuda):
+    w = synth.config1()
+    for s in (_settings(grid=48, sigma=1e-3), _settings(grid=1, grid_so2=1, thb_min=80.0, so2_min=0.6)):
+        run = hbtest.GpuRun(64, 64, s)
+        gpu = run(w.frames)
+        hbtest.assert_maps_close(gpu, hbtest.run_oracle(w.frames, "f32", s), f"{s['grid_thb']} {s['sigma']}")
+        run.close()
+
+
+def test_errors_and_empty_batch(torch_cuda):
+    import torch
+    from paper_1706_07263_amd import hb
+    d = hb.make_desc(64, 64, max_batch=2, grid_thb=8, grid_so2=8)
+    h = hb.hb_plan_create(d, 0)
+    fr = torch.zeros((3, 64, 64, 3), device="cuda")
+    out = torch.zeros((3, 64, 64), device="cuda")
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_estimate_frames(h, fr.data_ptr(), 1, [out.data_ptr()] * 4)
+    assert e.value.status == hb.HB_ERR_NO_FORWARD_MODEL
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_plan_get_info(h)
+    assert e.value.status == hb.HB_ERR_NO_FORWARD_MODEL
+    sp = synth.spectra()
+    hb.hb_set_forward_model(h, sp.eps_hb, sp.eps_hbo2, sp.response, sp.path_length_cm)
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_estimate_frames(h, fr.data_ptr(), 3, [out.data_ptr()] * 4)
+    assert e.value.status == hb.HB_ERR_BATCH
+    hb.hb_estimate_frames(h, fr.data_ptr(), 0, [out.data_ptr()] * 4)   # no-op
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_set_forward_model(h, sp.eps_hb, sp.eps_hbo2, np.zeros_like(sp.response), 0.1)
+    assert e.value.status == hb.HB_ERR_INVALID_ARG
+    # singular: E has rank 1 when both extinction curves are proportional and lambda = 0
+    d0 = hb.make_desc(64, 64, grid_thb=8, grid_so2=8, lam=0.0)
+    h0 = hb.hb_plan_create(d0, 0)
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_set_forward_model(h0, sp.eps_hb, 2 * sp.eps_hb, sp.response, 0.1)
+    assert e.value.status == hb.HB_ERR_ILL_POSED
+    hb.hb_destroy(h0)
+    assert hb.hb_plan_device_bytes(h) > 0
+    hb.hb_destroy(h)
+
+
+def test_null_maps_are_skipped(torch_cuda):
+    w = synth.config1()
+    run = hbtest.GpuRun(64, 64, w.plan)
+    full = run(w.frames)
+    part = run(w.frames, which=(False, True, False, True))
+    assert np.all(np.isnan(part[:, 0])) and np.all(np.isnan(part[:, 2]))
+    assert np.array_equal(part[:, 1], full[:, 1]) and np.array_equal(part[:, 3], full[:, 3], equal_nan=True)
+    run.close()
