@@ -153,8 +153,9 @@ hb_status_t hb_plan_get_timing(hb_plan_t plan, double ms[4], int64_t launches[4]
 /* Intermediate buffers of the last hb_estimate_frames call, for step-by-step
  * checks.  Synchronises the device, then copies `bytes` from the start of the
  * selected buffer of frame `frame` into host memory:
- *   HB_DEBUG_LOWPASS_OBS: float32 [3][LL], centred low-pass observation
- *       z_k = ybar_k - mu_ref_k (ybar = block mean of log-attenuation),
+ *   HB_DEBUG_LOWPASS_OBS: float32 [2][3][LL], centred low-pass observation
+ *       z_k = ybar_k - mu_ref_k (ybar = block mean of log-attenuation) as a
+ *       double-float: z_k = [0][k] + [1][k] (high and low parts),
  *       LL = (height >> levels) * (width >> levels), row-major blocks;
  *   HB_DEBUG_DETAILS: float32 [height][width][2], Tikhonov-inverted
  *       directional coefficients (Hb, HbO2) in the in-place Haar layout: the

@@ -13,9 +13,11 @@ namespace hb {
 
 // Posterior grid tiles: 8 x 8 nodes of the THb x SO2 grid.  One tile is
 //   [0]  Hb of the tile centre        [1]  HbO2 of the tile centre
-//   [2..4] lower corner of the tile's box in scaled log-attenuation space
-//   [5..7] upper corner                [8]  probe slot (int bits)   [9..15] pad
-//   [16 + 0*64 + i]  scaled, centred log-attenuation of node i, channel R
+//   [2..4] lower corner of the tile's box, relative to the tile centre
+//   [5..7] upper corner                [8]  probe slot (int bits)
+//   [9..11] tile centre in scaled, centred log-attenuation space (high part)
+//   [12..14] its low part (double-float)                          [15] pad
+//   [16 + 0*64 + i]  scaled log-attenuation of node i minus the centre, channel R
 //   [16 + 1*64 + i]  ... channel G
 //   [16 + 2*64 + i]  ... channel B
 //   [16 + 3*64 + i]  Hb of node i minus the tile centre
@@ -53,14 +55,14 @@ struct HaarArgs {
     float floor;
     float iref[3];           // float32 reference intensities exp(-mu_ref)
     const float *M;          // device, 6 floats (FP32 Tikhonov operator)
-    float *z;                // [n][3][LL]
+    float *z;                // [n][6][LL]: high parts R,G,B then low parts
     float2 *det;             // [n][H][W]
 };
 
 struct PosteriorArgs {
     long long LL;
     int n_frames;
-    const float *z;          // [n][3][LL]
+    const float *z;          // [n][6][LL]
     const float *tiles;      // [n_tiles][kTileFloats]
     int n_tiles;
     int split;

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "hb_df.h"
 #include "hb_internal.h"
 
 namespace hb {
@@ -173,13 +174,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
         __syncthreads();
     }
 
-    // 5. Centred low-pass observation z = ybar - mu_ref per block.
+    // 5. Centred low-pass observation z = ybar - mu_ref per block, as a
+    //    double-float: ybar - mu_ref = ln(I_ref / R) + mean(u).
     const float invB = 1.0f / (float)B;
     for (int i = tid; i < s.nb * 3; i += kBlockThreads) {
         const int k = i % 3, j = i / 3;
         const float R = (n > 0) ? s_r[k][j] : s_i[k][j];
-        const float zk = -log1pf((R - a.iref[k]) / a.iref[k]) + s_u[k][j << n] * invB;
-        a.z[((size_t)s.f * 3 + k) * d.LL + (size_t)s.br * d.wl + s.blk0 + j] = zk;
+        float zh, zl;
+        ln_ratio_df(a.iref[k], R, zh, zl);
+        df_add(zh, zl, s_u[k][j << n] * invB);
+        const size_t q = (size_t)s.br * d.wl + s.blk0 + j;
+        a.z[((size_t)s.f * 6 + k) * d.LL + q] = zh;
+        a.z[((size_t)s.f * 6 + 3 + k) * d.LL + q] = zl;
     }
 
     // 6. Tikhonov on every directional coefficient: (Hb, HbO2) = M * (R, G, B).
@@ -197,12 +203,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// K2: posterior mean over the grid for kPosteriorPix LL pixels per lane.
+// K2: posterior mean over the grid for PIX LL pixels per lane.
 //
 // Likelihood in base 2 with scaled coordinates: t_g = -|s z - s mu'_g|^2,
-// s = sqrt(log2(e) / (2 sigma^2)), mu' centred on mu_ref.  Node data are
-// wave-uniform and come through scalar loads.  The weights are taken relative
-// to a per-pixel reference m_ref that never changes inside the loop:
+// s = sqrt(log2(e) / (2 sigma^2)), mu' centred on mu_ref.  The observation
+// arrives as a double-float; per tile it is re-centred on the tile's centre
+// (double-float subtraction), so the per-node differences are formed from
+// small numbers and keep their precision.  Node data are wave-uniform and come
+// through scalar loads.  The weights are taken relative to a per-pixel
+// reference m_ref that never changes inside the loop:
 //   m_lo = best logit over one probe node per tile (a true logit, so the top
 //          weight is >= 1: no underflow of the whole sum);
 //   m_up = best upper bound over the tiles' boxes (>= every logit).
@@ -233,15 +242,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
     const int t0 = (int)((long long)a.n_tiles * split / S);
     const int t1 = (int)((long long)a.n_tiles * (split + 1) / S);
 
-    float zx[PIX], zy[PIX], zz[PIX];
-    const float *zf = a.z + (size_t)f * 3 * a.LL;
+    // Scaled observation s * z as a double-float per channel.
+    float zh[3][PIX], zl[3][PIX];
+    const float *zf = a.z + (size_t)f * 6 * a.LL;
 #pragma unroll
     for (int j = 0; j < PIX; ++j) {
         long long p = base + (long long)j * kBlockThreads;
         p = p < a.LL ? p : a.LL - 1;
-        zx[j] = a.scale * zf[p];
-        zy[j] = a.scale * zf[a.LL + p];
-        zz[j] = a.scale * zf[2 * a.LL + p];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float h = zf[k * a.LL + p], l = zf[(3 + k) * a.LL + p];
+            const float ph = a.scale * h;
+            zh[k][j] = ph;
+            zl[k][j] = fmaf(a.scale, h, -ph) + a.scale * l;
+        }
     }
 
     // Probe pass: m_lo, anchor, m_up.
@@ -255,23 +269,26 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
     }
     for (int t = t0; t < t1; ++t) {
         const float *__restrict__ T = a.tiles + (size_t)t * kTileFloats;
+        const float *__restrict__ N = T + kTileHdr;
         const int ps = __float_as_int(T[8]);
-        const float p0 = T[kTileHdr + ps], p1 = T[kTileHdr + kTileNodes + ps], p2 = T[kTileHdr + 2 * kTileNodes + ps];
-        const float phb = T[0] + T[kTileHdr + 3 * kTileNodes + ps];
-        const float pox = T[1] + T[kTileHdr + 4 * kTileNodes + ps];
-        const float lo0 = T[2], lo1 = T[3], lo2 = T[4], hi0 = T[5], hi1 = T[6], hi2 = T[7];
+        const float p0 = N[ps], p1 = N[kTileNodes + ps], p2 = N[2 * kTileNodes + ps];
+        const float phb = T[0] + N[3 * kTileNodes + ps];
+        const float pox = T[1] + N[4 * kTileNodes + ps];
 #pragma unroll
         for (int j = 0; j < PIX; ++j) {
-            const float d0 = zx[j] - p0, d1 = zy[j] - p1, d2 = zz[j] - p2;
+            const float r0 = (zh[0][j] - T[9]) + (zl[0][j] - T[12]);
+            const float r1 = (zh[1][j] - T[10]) + (zl[1][j] - T[13]);
+            const float r2 = (zh[2][j] - T[11]) + (zl[2][j] - T[14]);
+            const float d0 = r0 - p0, d1 = r1 - p1, d2 = r2 - p2;
             const float tp = -fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
             if (tp > mlo[j]) {
                 mlo[j] = tp;
                 ahb[j] = phb;
                 aox[j] = pox;
             }
-            const float e0 = fmaxf(fmaxf(lo0 - zx[j], zx[j] - hi0), 0.0f);
-            const float e1 = fmaxf(fmaxf(lo1 - zy[j], zy[j] - hi1), 0.0f);
-            const float e2 = fmaxf(fmaxf(lo2 - zz[j], zz[j] - hi2), 0.0f);
+            const float e0 = fmaxf(fmaxf(T[2] - r0, r0 - T[5]), 0.0f);
+            const float e1 = fmaxf(fmaxf(T[3] - r1, r1 - T[6]), 0.0f);
+            const float e2 = fmaxf(fmaxf(T[4] - r2, r2 - T[7]), 0.0f);
             mup[j] = fmaxf(mup[j], -fmaf(e0, e0, fmaf(e1, e1, e2 * e2)));
         }
     }
@@ -287,12 +304,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
 #pragma unroll
         for (int j = 0; j < PIX; ++j) mx[j] = mlo[j];
         for (int t = t0; t < t1; ++t) {
-            const float *__restrict__ T = a.tiles + (size_t)t * kTileFloats + kTileHdr;
+            const float *__restrict__ T = a.tiles + (size_t)t * kTileFloats;
+            const float *__restrict__ N = T + kTileHdr;
+            float r0[PIX], r1[PIX], r2[PIX];
+#pragma unroll
+            for (int j = 0; j < PIX; ++j) {
+                r0[j] = (zh[0][j] - T[9]) + (zl[0][j] - T[12]);
+                r1[j] = (zh[1][j] - T[10]) + (zl[1][j] - T[13]);
+                r2[j] = (zh[2][j] - T[11]) + (zl[2][j] - T[14]);
+            }
             for (int i = 0; i < kTileNodes; ++i) {
-                const float n0 = T[i], n1 = T[kTileNodes + i], n2 = T[2 * kTileNodes + i];
+                const float n0 = N[i], n1 = N[kTileNodes + i], n2 = N[2 * kTileNodes + i];
 #pragma unroll
                 for (int j = 0; j < PIX; ++j) {
-                    const float d0 = zx[j] - n0, d1 = zy[j] - n1, d2 = zz[j] - n2;
+                    const float d0 = r0[j] - n0, d1 = r1[j] - n1, d2 = r2[j] - n2;
                     mx[j] = fmaxf(mx[j], -fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
                 }
             }
@@ -308,16 +333,22 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
     for (int t = t0; t < t1; ++t) {
         const float *__restrict__ T = a.tiles + (size_t)t * kTileFloats;
         const float *__restrict__ N = T + kTileHdr;
+        float r0[PIX], r1[PIX], r2[PIX];
         float t0s[PIX], t1s[PIX], t2s[PIX];
 #pragma unroll
-        for (int j = 0; j < PIX; ++j) t0s[j] = t1s[j] = t2s[j] = 0.0f;
+        for (int j = 0; j < PIX; ++j) {
+            r0[j] = (zh[0][j] - T[9]) + (zl[0][j] - T[12]);
+            r1[j] = (zh[1][j] - T[10]) + (zl[1][j] - T[13]);
+            r2[j] = (zh[2][j] - T[11]) + (zl[2][j] - T[14]);
+            t0s[j] = t1s[j] = t2s[j] = 0.0f;
+        }
 #pragma unroll 16
         for (int i = 0; i < kTileNodes; ++i) {
             const float n0 = N[i], n1 = N[kTileNodes + i], n2 = N[2 * kTileNodes + i];
             const float dh = N[3 * kTileNodes + i], dx = N[4 * kTileNodes + i];
 #pragma unroll
             for (int j = 0; j < PIX; ++j) {
-                const float d0 = zx[j] - n0, d1 = zy[j] - n1, d2 = zz[j] - n2;
+                const float d0 = r0[j] - n0, d1 = r1[j] - n1, d2 = r2[j] - n2;
                 float tt = fmaf(-d0, d0, nref[j]);
                 tt = fmaf(-d1, d1, tt);
                 tt = fmaf(-d2, d2, tt);
@@ -358,8 +389,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float2 lowpass_estimate(const RecomposeArgs &a, int f, long long q) {
     if (a.lowpass == HB_LOWPASS_TIKHONOV) {
-        const float *zf = a.z + (size_t)f * 3 * a.d.LL;
-        const float z0 = zf[q], z1 = zf[a.d.LL + q], z2 = zf[2 * a.d.LL + q];
+        const long long LL = a.d.LL;
+        const float *zf = a.z + (size_t)f * 6 * LL;
+        const float z0 = zf[q] + zf[3 * LL + q], z1 = zf[LL + q] + zf[4 * LL + q];
+        const float z2 = zf[2 * LL + q] + zf[5 * LL + q];
         const float *M = a.M;
         return make_float2(M[6] + fmaf(M[0], z0, fmaf(M[1], z1, M[2] * z2)),
                            M[7] + fmaf(M[3], z0, fmaf(M[4], z1, M[5] * z2)));

@@ -180,6 +180,25 @@ void build_tiles(const hb_plan_desc_t &d, const ForwardModel &fm, const double m
                     mox += cox[slot];
                 }
             const float centre_hb = (float)(mhb / (na * nb)), centre_ox = (float)(mox / (na * nb));
+            // Scaled, centred log-attenuation of the real nodes, and their mean.
+            double mu_s[kTileNodes][3];
+            double cen[3] = {0, 0, 0};
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    const int slot = i * kTileSide + j;
+                    double m[3];
+                    fm.mu(chb[slot], cox[slot], m);
+                    for (int k = 0; k < 3; ++k) {
+                        mu_s[slot][k] = scale * (m[k] - mu_ref[k]);
+                        cen[k] += mu_s[slot][k];
+                    }
+                }
+            float cen_hi[3], cen_lo[3];
+            for (int k = 0; k < 3; ++k) {
+                const double c = cen[k] / (na * nb);
+                cen_hi[k] = (float)c;
+                cen_lo[k] = (float)(c - (double)cen_hi[k]);
+            }
             float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
             for (int slot = 0; slot < kTileNodes; ++slot) {
                 const int i = slot / kTileSide, j = slot % kTileSide;
@@ -189,10 +208,9 @@ void build_tiles(const hb_plan_desc_t &d, const ForwardModel &fm, const double m
                     N[4 * kTileNodes + slot] = 0.0f;
                     continue;
                 }
-                double m[3];
-                fm.mu(chb[slot], cox[slot], m);
                 for (int k = 0; k < 3; ++k) {
-                    const float v = (float)(scale * (m[k] - mu_ref[k]));
+                    const double c = (double)cen_hi[k] + (double)cen_lo[k];
+                    const float v = (float)(mu_s[slot][k] - c);
                     N[k * kTileNodes + slot] = v;
                     lo[k] = std::min(lo[k], v);
                     hi[k] = std::max(hi[k], v);
@@ -205,6 +223,8 @@ void build_tiles(const hb_plan_desc_t &d, const ForwardModel &fm, const double m
             for (int k = 0; k < 3; ++k) {
                 T[2 + k] = lo[k];
                 T[5 + k] = hi[k];
+                T[9 + k] = cen_hi[k];
+                T[12 + k] = cen_lo[k];
             }
             const int probe = ((na - 1) / 2) * kTileSide + (nb - 1) / 2;
             std::memcpy(&T[8], &probe, sizeof(int));
@@ -290,7 +310,7 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     st = HB_OK;
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_mf, sizeof(float) * 8);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_tiles, sizeof(float) * (size_t)p->n_tiles * kTileFloats);
-    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_z, sizeof(float) * nb * 3 * LL);
+    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_z, sizeof(float) * nb * 6 * LL);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_det, sizeof(float2) * nb * HW);
     if (st == HB_OK && desc->lowpass == HB_LOWPASS_BAYES)
         st = dev_alloc(p, (void **)&p->d_part, sizeof(float) * nb * p->split * kPartFields * LL);
@@ -530,8 +550,8 @@ hb_status_t hb_debug_copy(hb_plan_t p, int32_t which, int32_t frame, void *host_
     size_t avail = 0;
     switch (which) {
         case HB_DEBUG_LOWPASS_OBS:
-            src = p->d_z + (size_t)frame * 3 * LL;
-            avail = sizeof(float) * 3 * LL;
+            src = p->d_z + (size_t)frame * 6 * LL;
+            avail = sizeof(float) * 6 * LL;
             break;
         case HB_DEBUG_DETAILS:
             src = p->d_det + (size_t)frame * HW;

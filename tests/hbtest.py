@@ -91,7 +91,7 @@ class GpuRun:
         hb = self.hb
         LL = (self.h >> self.desc.levels) * (self.w >> self.desc.levels)
         if which == hb.HB_DEBUG_LOWPASS_OBS:
-            out = np.zeros((3, LL), np.float32)
+            out = np.zeros((2, 3, LL), np.float32)
         elif which == hb.HB_DEBUG_DETAILS:
             out = np.zeros((self.h, self.w, 2), np.float32)
         else:

@@ -55,8 +55,9 @@ def test_steps_match_oracle(torch_cuda):
     # low-pass observation: ybar - mu_ref per block
     y = -np.log(np.maximum(w.frames[0].astype(np.float64), 1e-4))
     ybar = y.reshape(32, 2, 32, 2, 3).mean(axis=(1, 3)).reshape(-1, 3)
-    z = run.debug(run.hb.HB_DEBUG_LOWPASS_OBS).T
-    assert np.max(np.abs(z - (ybar - info["mu_ref"]))) < 2e-7
+    zz = run.debug(run.hb.HB_DEBUG_LOWPASS_OBS).astype(np.float64)
+    z = (zz[0] + zz[1]).T
+    assert np.max(np.abs(z - (ybar - info["mu_ref"]))) < 3e-9
     # Tikhonov details in the in-place layout vs the oracle's Mallat layout
     det = run.debug(run.hb.HB_DEBUG_DETAILS)
     co = np.stack([orc.haar_forward(y[:, :, k], 1) for k in range(3)], axis=-1)
