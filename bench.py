@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample (0 = skip)")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -88,6 +90,15 @@ def main():
               "(each frame and each stream is independent: see the sharding notes)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if a.copy_calib_mib:
+        n = a.copy_calib_mib * (1 << 20) // 4
+        src = torch.arange(n, device="cuda:0", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": n * 4, "launches": 3}), flush=True)
+        return
     from paper_1706_07263_amd import build as hb_build
     if not os.path.exists(hb_build.LIB):
         import __graft_entry__
@@ -127,6 +138,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms, launches = hb.hb_plan_get_timing(plan.handle)
+    evaluated, full = hb.hb_plan_get_work(plan.handle)
     hb.hb_plan_set_timing(plan.handle, False)
     log(f"timed {a.steps} steps in {elapsed:.3f} s; stage ms {ms / np.maximum(launches, 1)}", a.quiet)
 
@@ -134,11 +146,16 @@ def main():
     LL = (H >> a.levels) * (W >> a.levels)
     pairs_per_launch = B * LL * a.grid * a.grid
     k2_s = ms[1] / max(launches[1], 1) / 1e3
-    achieved = pairs_per_launch * FLOPS_PER_PAIR / k2_s / 1e12
+    # Evaluated pairs per launch (chunks whose weights are exactly zero are
+    # skipped; the flops of the roofline are those actually executed).
+    eval_per_launch = evaluated / max(launches[1], 1) if evaluated else pairs_per_launch
+    achieved = eval_per_launch * FLOPS_PER_PAIR / k2_s / 1e12
     roofline = {"bound": "alu", "kernel": "k_posterior", "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                 "traffic": None, "avg_launch_ms": round(k2_s * 1e3, 4),
-                "pairs_per_s": pairs_per_launch / k2_s,
+                "evaluated_pairs_per_launch": int(eval_per_launch), "full_grid_pairs_per_launch": pairs_per_launch,
+                "evaluated_pairs_per_s": eval_per_launch / k2_s,
+                "full_grid_pairs_per_s": pairs_per_launch / k2_s,
                 "flops_per_pair": FLOPS_PER_PAIR, "exps_per_pair": EXPS_PER_PAIR}
     stage = {"log_haar_ms": ms[0] / max(launches[0], 1), "posterior_ms": ms[1] / max(launches[1], 1),
              "recompose_ms": ms[2] / max(launches[2], 1), "call_ms": ms[3] / max(launches[3], 1)}
@@ -157,7 +174,8 @@ def main():
         "config": {"workload": f"1920x1080 video frames, {a.levels} Haar levels, {a.grid}x{a.grid} "
                                f"THb x SO2 posterior grid, {a.dtype} frames",
                    "global_batch": B, "frame": "1920x1080", "levels": a.levels,
-                   "grid": f"{a.grid}x{a.grid}", "grid_split": info["grid_split"], "parallelism": "1 GPU"},
+                   "grid": f"{a.grid}x{a.grid}", "grid_split": info["grid_split"],
+                   "posterior_kernel": info["posterior_kernel"], "parallelism": "1 GPU"},
         "mpixel_per_s": round(fps * H * W / 1e6, 2),
         "stages_ms_per_call": {k: round(v, 4) for k, v in stage.items()},
         "roofline": roofline,

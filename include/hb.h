@@ -73,7 +73,8 @@ typedef struct {
     double ref_thb, ref_so2;    /* linearisation point of E; NaN = grid centre            */
     double thb_eps;             /* SO2 is NaN where THb <= thb_eps (uM)                    */
     int32_t lowpass;            /* hb_lowpass_t                                            */
-    int32_t grid_split;         /* posterior grid split across workgroups; 0 = automatic   */
+    int32_t grid_split;         /* posterior grid split across workgroups; 0 = automatic
+                                   (sized so that max_batch frames fill the GPU)         */
 } hb_plan_desc_t;
 
 /* Camera sensitivities and attenuation spectra (the camera matrix C and the
@@ -101,7 +102,8 @@ typedef struct {
     double ref_hb, ref_hbo2;
     double mu_ref[3];     /* centring offset: -ln of the float32 reference intensities                 */
     int32_t grid_split;   /* posterior grid split in use                                                */
-    int32_t n_tiles;      /* 8x8-node grid tiles                                                        */
+    int32_t n_tiles;      /* grid super-tiles                                                           */
+    int32_t posterior_kernel; /* 0 = MFMA logits, 1 = direct VALU (grids too coarse for the former)     */
     int64_t n_nodes;
 } hb_plan_info_t;
 
@@ -149,6 +151,16 @@ hb_status_t hb_plan_get_info(hb_plan_t plan, hb_plan_info_t *info);
  * and clears the record. */
 hb_status_t hb_plan_set_timing(hb_plan_t plan, int32_t enable);
 hb_status_t hb_plan_get_timing(hb_plan_t plan, double ms[4], int64_t launches[4]);
+
+/* Posterior work of the calls made since the last hb_plan_set_timing
+ * (counted only while timing is enabled): `evaluated` = (LL pixel, grid node)
+ * pairs the posterior kernel actually evaluated, `full` = LL pixels x grid
+ * nodes of those calls.  The MFMA kernel leaves out 16-node chunks whose
+ * weights are exactly zero in float32 for every pixel of a wave (their box
+ * bound is more than 160 below each pixel's reference logit), so
+ * evaluated <= full while the results are unchanged bit for bit.
+ * Synchronises the device. */
+hb_status_t hb_plan_get_work(hb_plan_t plan, int64_t *evaluated, int64_t *full);
 
 /* Intermediate buffers of the last hb_estimate_frames call, for step-by-step
  * checks.  Synchronises the device, then copies `bytes` from the start of the

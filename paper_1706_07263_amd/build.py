@@ -17,6 +17,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     # No packed FP32 instructions anywhere in device code.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results straight into VGPRs (the posterior kernel feeds them to the
+    # VALU; AGPR results would need an extra move per value).
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

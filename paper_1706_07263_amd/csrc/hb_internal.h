@@ -11,30 +11,60 @@
 
 namespace hb {
 
-// Posterior grid tiles: 8 x 8 nodes of the THb x SO2 grid.  One tile is
-//   [0]  Hb of the tile centre        [1]  HbO2 of the tile centre
-//   [2..4] lower corner of the tile's box, relative to the tile centre
-//   [5..7] upper corner                [8]  probe slot (int bits)
-//   [9..11] tile centre in scaled, centred log-attenuation space (high part)
-//   [12..14] its low part (double-float)                          [15] pad
-//   [16 + 0*64 + i]  scaled log-attenuation of node i minus the centre, channel R
-//   [16 + 1*64 + i]  ... channel G
-//   [16 + 2*64 + i]  ... channel B
-//   [16 + 3*64 + i]  Hb of node i minus the tile centre
-//   [16 + 4*64 + i]  HbO2 of node i minus the tile centre
-// Unused slots of edge tiles sit far away (weight exactly 0) with zero offsets.
-constexpr int kTileSide = 8;
-constexpr int kTileNodes = kTileSide * kTileSide;
-constexpr int kTileHdr = 16;
-constexpr int kTileFloats = kTileHdr + 5 * kTileNodes;
-constexpr float kPadCoord = 1.0e18f;
+// Posterior grid super-tiles: SUP x SUP nodes of the THb x SO2 grid (SUP is
+// 8, 16 or 32), cut into 4 x 4-node chunks of 16 nodes.  Coordinates are
+// scaled log-attenuations centred on mu_ref; inside a super-tile they are
+// stored relative to the super-tile centre.  One super-tile is
+//   header (kSupHdr floats)
+//     [0..2]  centre, high parts        [3..5] centre, low parts (double-float)
+//     [6] Hb of the centre node set     [7] HbO2 of it (moments are relative to these)
+//     [8..10] box lower corner          [11..13] box upper corner (relative)
+//     [14] number of probes (int bits)
+//   probes (kMaxProbes x kProbeFloats): relative coordinates (3), Hb, HbO2
+//   chunks (kChunkFloats each), node j = 4 * (THb offset) + (SO2 offset):
+//     [0 + 16k + j], k = 0..2: relative coordinate k of node j
+//     [48 + j]: minus the squared norm of the relative coordinates of node j
+//     Slots outside the grid hold kPadCoord coordinates and kPadLogit here.
+//     [64 + j]: Hb of node j minus header[6]     [80 + j]: HbO2 minus header[7]
+//     [96..98] chunk box lower corner, [99..101] upper corner (relative)
+// The first 64 floats of a chunk are exactly the B operand of a 16x16x4 MFMA
+// (lane l reads float l: row k = l / 16, column j = l % 16); the A operand
+// carries twice the pixel's relative coordinates.
+// Precision rule for the MFMA kernel.  Its expanded logit rounds at the scale
+// of the squared super-tile radius R^2 (scaled units), and a coarse grid
+// (node spacing h in uM of Hb/HbO2) turns a logit error into an estimate error
+// of about R^2 h u with little averaging.  The MFMA kernel is used when
+// R^2 h <= kMfmaPrecisionBudget, the direct kernel otherwise (both meet the
+// parity tolerance; the bound was set from the measured parity errors).
+constexpr double kMfmaPrecisionBudget = 1000.0;
+constexpr int kChunkNodes = 16;
+constexpr int kSupHdr = 32;
+constexpr int kMaxProbes = 16;
+constexpr int kProbeFloats = 8;
+constexpr int kChunkFloats = 104;
+constexpr float kPadLogit = -1.0e30f;
+// Coordinates of slots outside the grid: far from every observation (weight
+// exactly 0 in the difference form) yet small enough for the MFMA operands.
+constexpr float kPadCoord = 1.0e4f;
+
+// Side of a super-tile: about 1/8 of the grid (multiple of 4, 4..32).  The
+// expanded logit loses precision with the squared extent of the super-tile in
+// log-attenuation space, so coarse grids get small super-tiles.
+inline int super_side(int grid_thb, int grid_so2) {
+    const int g = grid_thb < grid_so2 ? grid_thb : grid_so2;
+    const int side = 4 * (g / 32);
+    return side < 4 ? 4 : (side > 32 ? 32 : side);
+}
+inline int super_floats(int side) {
+    return kSupHdr + kMaxProbes * kProbeFloats + (side / 4) * (side / 4) * kChunkFloats;
+}
 
 // Strip of pixels one workgroup of the Haar kernels stages in LDS.
 constexpr int kStripPixels = 2048;
 constexpr int kBlockThreads = 256;
 
-// LL pixels per thread in the posterior kernel.
-constexpr int kPosteriorPix = 4;
+// Pixel blocks of 16 per wave in the posterior kernel.
+constexpr int kPixelBlocks = 2;
 
 // Partial moments per LL pixel and grid split:
 //   [0] logit reference, [1] S0, [2] S1 about the anchor, [3] S2 about the anchor,
@@ -61,13 +91,17 @@ struct HaarArgs {
 
 struct PosteriorArgs {
     long long LL;
+    int hl, wl;              // low-pass band size (LL = hl * wl)
     int n_frames;
     const float *z;          // [n][6][LL]
-    const float *tiles;      // [n_tiles][kTileFloats]
-    int n_tiles;
+    const float *supers;     // [n_supers][super_floats(side)]
+    int n_supers;
+    int super_stride;        // floats
+    int chunks_per_super;
     int split;
     float scale;             // sqrt(log2(e) / (2 sigma^2))
     float *part;             // [n][split][kPartFields][LL]
+    unsigned long long *work;  // optional: pairs evaluated (pixel x node), added per wave
 };
 
 struct RecomposeArgs {
@@ -86,7 +120,7 @@ struct RecomposeArgs {
 // Launchers (hb_kernels.hip).  They only enqueue work.
 hipError_t launch_tikhonov_fp64(const double *d_in, double *d_out, float *d_mf, hipStream_t s);
 hipError_t launch_log_haar(const void *frames, int n_frames, const HaarArgs &a, hipStream_t s);
-hipError_t launch_posterior(const PosteriorArgs &a, hipStream_t s);
+hipError_t launch_posterior(const PosteriorArgs &a, bool mfma, hipStream_t s);
 hipError_t launch_recompose(int n_frames, const RecomposeArgs &a, hipStream_t s);
 
 }  // namespace hb

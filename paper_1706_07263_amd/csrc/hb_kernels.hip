@@ -203,25 +203,29 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// K2: posterior mean over the grid for PIX LL pixels per lane.
+// K2: posterior mean over the grid on the low-pass band.
 //
-// Likelihood in base 2 with scaled coordinates: t_g = -|s z - s mu'_g|^2,
-// s = sqrt(log2(e) / (2 sigma^2)), mu' centred on mu_ref.  The observation
-// arrives as a double-float; per tile it is re-centred on the tile's centre
-// (double-float subtraction), so the per-node differences are formed from
-// small numbers and keep their precision.  Node data are wave-uniform and come
-// through scalar loads.  The weights are taken relative to a per-pixel
-// reference m_ref that never changes inside the loop:
-//   m_lo = best logit over one probe node per tile (a true logit, so the top
-//          weight is >= 1: no underflow of the whole sum);
-//   m_up = best upper bound over the tiles' boxes (>= every logit).
-// If m_up - m_lo <= kFarGap for every lane of the wave, m_ref = m_lo and all
-// weights lie in [0, 2^kFarGap]; otherwise the wave first takes the exact
-// maximum over its nodes.  Moments are centred on the tile centre inside a
-// tile and on the best probe node (the anchor) across tiles; tile sums are
-// merged with Kahan compensation.
+// Likelihood in base 2 with scaled coordinates: t_g = -|s z - s mu'_g|^2 with
+// s = sqrt(log2(e) / (2 sigma^2)) and mu' centred on mu_ref.  Inside a
+// super-tile both the observation r = s z - centre (formed from the
+// double-float observation) and the node coordinates v_g are small.
+//
+// The weights are taken relative to a per-pixel reference m fixed before the
+// main loop: m_lo = best logit of one probe node per 8 x 8 patch (a true
+// logit, so the top weight is >= 1 and the sum cannot underflow), m_up = best
+// upper bound over the super-tiles' boxes.  If m_up - m_lo <= kFarGap for the
+// whole wave, m = m_lo and every weight lies in [0, 2^kFarGap]; otherwise the
+// wave first takes the exact maximum over its nodes.  Moments are accumulated
+// relative to the super-tile's centre inside a super-tile, then merged with
+// Kahan compensation relative to the pixel's anchor (its best probe node).
+//
+// Two kernels share this: k_posterior (MFMA logits, used when every
+// super-tile is compact in scaled units) and k_posterior_direct (VALU
+// difference form, for grids too coarse for the expanded logit's precision).
 // ---------------------------------------------------------------------------
 constexpr float kFarGap = 64.0f;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
     const float y = x - c;
@@ -230,155 +234,362 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
     s = t;
 }
 
-template <int PIX>
-__global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
-    const int S = a.split;
-    const int split = blockIdx.x % S;
-    const int chunk = blockIdx.x / S;
-    const long long per_block = (long long)kBlockThreads * PIX;
-    const int chunks_per_frame = (int)((a.LL + per_block - 1) / per_block);
-    const int f = chunk / chunks_per_frame;
-    const long long base = (long long)(chunk % chunks_per_frame) * per_block + threadIdx.x;
-    const int t0 = (int)((long long)a.n_tiles * split / S);
-    const int t1 = (int)((long long)a.n_tiles * (split + 1) / S);
+__device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
-    // Scaled observation s * z as a double-float per channel.
-    float zh[3][PIX], zl[3][PIX];
-    const float *zf = a.z + (size_t)f * 6 * a.LL;
+// A wave takes a compact 8-wide tile of LL pixels (PW / 8 rows), four waves
+// of a workgroup stack vertically; compact tiles keep the wave's observations
+// close together, which is what the skipping test below relies on.
+constexpr int kWaveTileW = 8;
+
+struct WaveWork {
+    int f, split, s0, s1;
+    int r0, c0;  // wave tile origin in LL pixels
+};
+
+template <int PW>
+__device__ __forceinline__ WaveWork wave_work(const PosteriorArgs &a) {
+    constexpr int TH = PW / kWaveTileW;
+    WaveWork w;
+    const int wave = threadIdx.x >> 6;
+    const int S = a.split;
+    w.split = blockIdx.x % S;
+    const int chunk = blockIdx.x / S;
+    const int bcols = (a.wl + kWaveTileW - 1) / kWaveTileW;
+    const int brows = (a.hl + 4 * TH - 1) / (4 * TH);
+    const int per_frame = bcols * brows;
+    w.f = chunk / per_frame;
+    const int t = chunk % per_frame;
+    w.r0 = (t / bcols) * 4 * TH + wave * TH;
+    w.c0 = (t % bcols) * kWaveTileW;
+    w.s0 = (int)((long long)a.n_supers * w.split / S);
+    w.s1 = (int)((long long)a.n_supers * (w.split + 1) / S);
+    return w;
+}
+
+// LL index of the wave's i-th pixel (clamped into the image) and whether it exists.
+__device__ __forceinline__ bool wave_pixel(const PosteriorArgs &a, const WaveWork &w, int i, long long &p) {
+    const int r = w.r0 + i / kWaveTileW, c = w.c0 + i % kWaveTileW;
+    const bool valid = r < a.hl && c < a.wl;
+    p = (long long)min(r, a.hl - 1) * a.wl + min(c, a.wl - 1);
+    return valid;
+}
+
+// Scaled double-float observation of LL pixel p, channel k.
+__device__ __forceinline__ void load_obs(const float *zf, long long LL, long long p, int k, float sc,
+                                         float &h, float &l) {
+    const float zh = zf[k * LL + p], zl = zf[(3 + k) * LL + p];
+    h = sc * zh;
+    l = fmaf(sc, zh, -h) + sc * zl;
+}
+
+__device__ __forceinline__ void recentre(const float *T, const float ph[3], const float pl[3], float r[3]) {
 #pragma unroll
-    for (int j = 0; j < PIX; ++j) {
-        long long p = base + (long long)j * kBlockThreads;
-        p = p < a.LL ? p : a.LL - 1;
+    for (int k = 0; k < 3; ++k) r[k] = (ph[k] - T[k]) + (pl[k] - T[3 + k]);
+}
+
+// Upper bound of the logit over an axis-aligned box [lo, hi] (6 floats).
+__device__ __forceinline__ float box_bound(const float *box, const float r[3]) {
+    const float e0 = fmaxf(fmaxf(box[0] - r[0], r[0] - box[3]), 0.0f);
+    const float e1 = fmaxf(fmaxf(box[1] - r[1], r[1] - box[4]), 0.0f);
+    const float e2 = fmaxf(fmaxf(box[2] - r[2], r[2] - box[5]), 0.0f);
+    return -fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+}
+
+// Upper bound of the logit between two boxes (6 floats each: lo[3], hi[3]).
+__device__ __forceinline__ float box_box_bound(const float *box, const float r[6]) {
+    const float e0 = fmaxf(fmaxf(box[0] - r[3], r[0] - box[3]), 0.0f);
+    const float e1 = fmaxf(fmaxf(box[1] - r[4], r[1] - box[4]), 0.0f);
+    const float e2 = fmaxf(fmaxf(box[2] - r[5], r[2] - box[5]), 0.0f);
+    return -fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+}
+
+// exp2 of anything below -kSkipLog2 is exactly 0 in float32 (the smallest
+// subnormal is 2^-149); the margin covers rounding of bounds and logits.
+constexpr float kSkipLog2 = 160.0f;
+// Widening of the observation box for the rounding of high + low parts.
+constexpr float kBoxSlack = 1.0e-3f;
+
+struct PixelRef {
+    float m, ahb, aox;
+};
+
+// Per-pixel reference logit and anchor.  Each pixel is handled by LPP lanes
+// (lane / PW selects the part), which split the super-tiles between them.
+template <int PW, int LPP>
+__device__ PixelRef pixel_reference(const PosteriorArgs &a, const WaveWork &w, const float ph[3],
+                                    const float pl[3], int part) {
+    float mlo = -INFINITY, mup = -INFINITY, ahb = 0.0f, aox = 0.0f;
+    for (int si = w.s0 + part; si < w.s1; si += LPP) {
+        const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+        float r[3];
+        recentre(T, ph, pl, r);
+        mup = fmaxf(mup, box_bound(T + 8, r));
+        const int np = __float_as_int(T[14]);
+        for (int i = 0; i < np; ++i) {
+            const float *P = T + kSupHdr + i * kProbeFloats;
+            const float d0 = r[0] - P[0], d1 = r[1] - P[1], d2 = r[2] - P[2];
+            const float tp = -fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+            if (tp > mlo) {
+                mlo = tp;
+                ahb = P[3];
+                aox = P[4];
+            }
+        }
+    }
+    if (LPP == 2) {  // combine the two halves (lower half wins ties)
+        const float om = __shfl_xor(mlo, PW), oh = __shfl_xor(ahb, PW), oo = __shfl_xor(aox, PW);
+        const float ou = __shfl_xor(mup, PW);
+        const bool take = part == 0 ? (om > mlo) : !(mlo > om);
+        if (take) {
+            mlo = om;
+            ahb = oh;
+            aox = oo;
+        }
+        mup = fmaxf(mup, ou);
+    }
+    PixelRef ref{mlo, ahb, aox};
+    if (__any(!(mup - mlo <= kFarGap))) {
+        // Exact maximum over this split's nodes, difference form.
+        float mx = mlo;
+        for (int si = w.s0 + part; si < w.s1; si += LPP) {
+            const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+            float r[3];
+            recentre(T, ph, pl, r);
+            const float *__restrict__ C = T + kSupHdr + kMaxProbes * kProbeFloats;
+            for (int c = 0; c < a.chunks_per_super; ++c, C += kChunkFloats)
+                for (int j = 0; j < kChunkNodes; ++j) {
+                    const float d0 = r[0] - C[j], d1 = r[1] - C[16 + j], d2 = r[2] - C[32 + j];
+                    mx = fmaxf(mx, -fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
+                }
+        }
+        if (LPP == 2) mx = fmaxf(mx, __shfl_xor(mx, PW));
+        ref.m = mx;
+    }
+    return ref;
+}
+
+// MFMA kernel: a wave takes PB blocks of 16 LL pixels.  Per super-tile and
+// 16-node chunk one v_mfma_f32_16x16x4_f32 forms the 16 x 16 logits
+//   t - m = [2 r, 1] . [v_g, -|v_g|^2] + (-(|r|^2 + m)),
+// whose per-pixel constant (the accumulator input) comes from one more MFMA
+// of [r0^2, r1^2, r2^2, m] against -1 per super-tile.  Each lane then holds 4
+// pixels x 1 node of the result (lane l: node l % 16, pixels 4 (l / 16) + q)
+// and runs the exponentials and the three moments on the VALU.
+template <int PB>
+__global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
+    constexpr int PW = 16 * PB;
+    constexpr int LPP = 64 / PW;
+    const int lane = threadIdx.x & 63;
+    const int lp = lane & 15, lk = lane >> 4;
+    const WaveWork w = wave_work<PW>(a);
+    const float *zf = a.z + (size_t)w.f * 6 * a.LL;
+    const float sc = a.scale;
+
+    // Per-pixel pass: lane -> pixel lane % PW of the wave tile.
+    const int part = lane / PW;
+    float ph[3], pl[3];
+    {
+        long long p;
+        wave_pixel(a, w, lane % PW, p);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) load_obs(zf, a.LL, p, k, sc, ph[k], pl[k]);
+    }
+    const PixelRef ref = pixel_reference<PW, LPP>(a, w, ph, pl, part);
+
+    // A operand of block b: lane (lp, lk) holds coordinate lk of pixel b*16 + lp
+    // (lk == 3: the homogeneous 1, and m for the constant term).
+    float ah[PB], al[PB], am[PB];
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+        long long p;
+        wave_pixel(a, w, b * 16 + lp, p);
+        load_obs(zf, a.LL, p, lk < 3 ? lk : 0, sc, ah[b], al[b]);
+        am[b] = __shfl(ref.m, b * 16 + lp);
+    }
+    // Accumulator layout: lane (lp, lk) holds pixels b*16 + 4*lk + q, node lp.
+    float anc_hb[PB][4], anc_ox[PB][4];
+#pragma unroll
+    for (int b = 0; b < PB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            anc_hb[b][q] = __shfl(ref.ahb, b * 16 + 4 * lk + q);
+            anc_ox[b][q] = __shfl(ref.aox, b * 16 + 4 * lk + q);
+        }
+    float R0[PB][4], R1[PB][4], R2[PB][4], K0[PB][4], K1[PB][4], K2[PB][4];
+#pragma unroll
+    for (int b = 0; b < PB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) R0[b][q] = R1[b][q] = R2[b][q] = K0[b][q] = K1[b][q] = K2[b][q] = 0.0f;
+
+    // Exact skipping.  A chunk (or super-tile) whose logit upper bound lies
+    // more than kSkipLog2 below every pixel's reference contributes weights
+    // that are exactly 0 in float32, so leaving it out changes no bit.  The
+    // bound is taken between the chunk's box and the box of the wave's
+    // observations (min reference over the wave), one chunk per lane.
+    float zlo[3], zhi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) zlo[k] = zhi[k] = ph[k] + pl[k];
+    float mmin = ref.m;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float h = zf[k * a.LL + p], l = zf[(3 + k) * a.LL + p];
-            const float ph = a.scale * h;
-            zh[k][j] = ph;
-            zl[k][j] = fmaf(a.scale, h, -ph) + a.scale * l;
+            zlo[k] = fminf(zlo[k], __shfl_xor(zlo[k], o));
+            zhi[k] = fmaxf(zhi[k], __shfl_xor(zhi[k], o));
         }
+        mmin = fminf(mmin, __shfl_xor(mmin, o));
     }
-
-    // Probe pass: m_lo, anchor, m_up.
-    float mlo[PIX], mup[PIX], ahb[PIX], aox[PIX];
+    const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+    unsigned executed = 0;   // chunks evaluated by this wave
+    for (int si = w.s0; si < w.s1; ++si) {
+        const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+        float rbox[6];
 #pragma unroll
-    for (int j = 0; j < PIX; ++j) {
-        mlo[j] = -INFINITY;
-        mup[j] = -INFINITY;
-        ahb[j] = 0.0f;
-        aox[j] = 0.0f;
-    }
-    for (int t = t0; t < t1; ++t) {
-        const float *__restrict__ T = a.tiles + (size_t)t * kTileFloats;
-        const float *__restrict__ N = T + kTileHdr;
-        const int ps = __float_as_int(T[8]);
-        const float p0 = N[ps], p1 = N[kTileNodes + ps], p2 = N[2 * kTileNodes + ps];
-        const float phb = T[0] + N[3 * kTileNodes + ps];
-        const float pox = T[1] + N[4 * kTileNodes + ps];
-#pragma unroll
-        for (int j = 0; j < PIX; ++j) {
-            const float r0 = (zh[0][j] - T[9]) + (zl[0][j] - T[12]);
-            const float r1 = (zh[1][j] - T[10]) + (zl[1][j] - T[13]);
-            const float r2 = (zh[2][j] - T[11]) + (zl[2][j] - T[14]);
-            const float d0 = r0 - p0, d1 = r1 - p1, d2 = r2 - p2;
-            const float tp = -fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-            if (tp > mlo[j]) {
-                mlo[j] = tp;
-                ahb[j] = phb;
-                aox[j] = pox;
-            }
-            const float e0 = fmaxf(fmaxf(T[2] - r0, r0 - T[5]), 0.0f);
-            const float e1 = fmaxf(fmaxf(T[3] - r1, r1 - T[6]), 0.0f);
-            const float e2 = fmaxf(fmaxf(T[4] - r2, r2 - T[7]), 0.0f);
-            mup[j] = fmaxf(mup[j], -fmaf(e0, e0, fmaf(e1, e1, e2 * e2)));
+        for (int k = 0; k < 3; ++k) {
+            const float c = T[k] + T[3 + k];
+            rbox[k] = (zlo[k] - c) - kBoxSlack;
+            rbox[3 + k] = (zhi[k] - c) + kBoxSlack;
         }
-    }
-    bool far = false;
+        if (!(box_box_bound(T + 8, rbox) - mmin > -kSkipLog2)) continue;
+        const int kk = lk < 3 ? lk : 0;
+        const float ch = T[kk], cl = T[3 + kk];
+        float av[PB];
+        f32x4 cv[PB];
 #pragma unroll
-    for (int j = 0; j < PIX; ++j) far |= !(mup[j] - mlo[j] <= kFarGap);
-    float nref[PIX];
+        for (int b = 0; b < PB; ++b) {
+            const float r = (ah[b] - ch) + (al[b] - cl);
+            av[b] = lk < 3 ? 2.0f * r : 1.0f;
+            const float a2 = lk < 3 ? r * r : am[b];
+            cv[b] = mfma_16x16x4(a2, -1.0f, zero4);   // -(|r|^2 + m) per pixel row
+        }
+        float L0[PB][4], L1[PB][4], L2[PB][4];
 #pragma unroll
-    for (int j = 0; j < PIX; ++j) nref[j] = -mlo[j];
-    if (__any(far)) {
-        // Exact maximum over this split's nodes.
-        float mx[PIX];
+        for (int b = 0; b < PB; ++b)
 #pragma unroll
-        for (int j = 0; j < PIX; ++j) mx[j] = mlo[j];
-        for (int t = t0; t < t1; ++t) {
-            const float *__restrict__ T = a.tiles + (size_t)t * kTileFloats;
-            const float *__restrict__ N = T + kTileHdr;
-            float r0[PIX], r1[PIX], r2[PIX];
+            for (int q = 0; q < 4; ++q) L0[b][q] = L1[b][q] = L2[b][q] = 0.0f;
+        const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
+        for (int cg = 0; cg < a.chunks_per_super; cg += 64) {
+            const int ct = min(cg + lane, a.chunks_per_super - 1);
+            const bool keep = cg + lane < a.chunks_per_super &&
+                              box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > -kSkipLog2;
+            unsigned long long mask = __ballot(keep);
+            while (mask) {
+                const int c = cg + __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const float *__restrict__ C = C0 + (size_t)c * kChunkFloats;
+                ++executed;
+                const float bv = C[lane];
+                const float mh = C[64 + lp], mo = C[80 + lp];
 #pragma unroll
-            for (int j = 0; j < PIX; ++j) {
-                r0[j] = (zh[0][j] - T[9]) + (zl[0][j] - T[12]);
-                r1[j] = (zh[1][j] - T[10]) + (zl[1][j] - T[13]);
-                r2[j] = (zh[2][j] - T[11]) + (zl[2][j] - T[14]);
-            }
-            for (int i = 0; i < kTileNodes; ++i) {
-                const float n0 = N[i], n1 = N[kTileNodes + i], n2 = N[2 * kTileNodes + i];
+                for (int b = 0; b < PB; ++b) {
+                    const f32x4 d = mfma_16x16x4(av[b], bv, cv[b]);
 #pragma unroll
-                for (int j = 0; j < PIX; ++j) {
-                    const float d0 = r0[j] - n0, d1 = r1[j] - n1, d2 = r2[j] - n2;
-                    mx[j] = fmaxf(mx[j], -fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
+                    for (int q = 0; q < 4; ++q) {
+                        const float wt = __builtin_amdgcn_exp2f(d[q]);
+                        L0[b][q] += wt;
+                        L1[b][q] = fmaf(wt, mh, L1[b][q]);
+                        L2[b][q] = fmaf(wt, mo, L2[b][q]);
+                    }
                 }
             }
         }
+        const float chb = T[6], cox = T[7];
 #pragma unroll
-        for (int j = 0; j < PIX; ++j) nref[j] = -mx[j];
+        for (int b = 0; b < PB; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                kahan_add(R0[b][q], K0[b][q], L0[b][q]);
+                kahan_add(R1[b][q], K1[b][q], fmaf(chb - anc_hb[b][q], L0[b][q], L1[b][q]));
+                kahan_add(R2[b][q], K2[b][q], fmaf(cox - anc_ox[b][q], L0[b][q], L2[b][q]));
+            }
     }
 
-    // Main pass.
-    float s0[PIX], s1[PIX], s2[PIX], c0[PIX], c1[PIX], c2[PIX];
+    if (a.work && lane == 0) atomicAdd(a.work, (unsigned long long)executed * PW * kChunkNodes);
+
+    // Reduce over the 16 node lanes of each row, then lanes with lp == 0 write.
 #pragma unroll
-    for (int j = 0; j < PIX; ++j) s0[j] = s1[j] = s2[j] = c0[j] = c1[j] = c2[j] = 0.0f;
-    for (int t = t0; t < t1; ++t) {
-        const float *__restrict__ T = a.tiles + (size_t)t * kTileFloats;
-        const float *__restrict__ N = T + kTileHdr;
-        float r0[PIX], r1[PIX], r2[PIX];
-        float t0s[PIX], t1s[PIX], t2s[PIX];
+    for (int b = 0; b < PB; ++b)
 #pragma unroll
-        for (int j = 0; j < PIX; ++j) {
-            r0[j] = (zh[0][j] - T[9]) + (zl[0][j] - T[12]);
-            r1[j] = (zh[1][j] - T[10]) + (zl[1][j] - T[13]);
-            r2[j] = (zh[2][j] - T[11]) + (zl[2][j] - T[14]);
-            t0s[j] = t1s[j] = t2s[j] = 0.0f;
+        for (int q = 0; q < 4; ++q) {
+            float x0 = R0[b][q], x1 = R1[b][q], x2 = R2[b][q];
+#pragma unroll
+            for (int o = 8; o >= 1; o >>= 1) {
+                x0 += __shfl_xor(x0, o);
+                x1 += __shfl_xor(x1, o);
+                x2 += __shfl_xor(x2, o);
+            }
+            R0[b][q] = x0;
+            R1[b][q] = x1;
+            R2[b][q] = x2;
         }
-#pragma unroll 16
-        for (int i = 0; i < kTileNodes; ++i) {
-            const float n0 = N[i], n1 = N[kTileNodes + i], n2 = N[2 * kTileNodes + i];
-            const float dh = N[3 * kTileNodes + i], dx = N[4 * kTileNodes + i];
+    float *out = a.part + ((size_t)w.f * a.split + w.split) * kPartFields * a.LL;
 #pragma unroll
-            for (int j = 0; j < PIX; ++j) {
-                const float d0 = r0[j] - n0, d1 = r1[j] - n1, d2 = r2[j] - n2;
-                float tt = fmaf(-d0, d0, nref[j]);
-                tt = fmaf(-d1, d1, tt);
-                tt = fmaf(-d2, d2, tt);
-                const float w = __builtin_amdgcn_exp2f(tt);
-                t0s[j] += w;
-                t1s[j] = fmaf(w, dh, t1s[j]);
-                t2s[j] = fmaf(w, dx, t2s[j]);
+    for (int b = 0; b < PB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int src = b * 16 + 4 * lk + q;
+            const float m = __shfl(ref.m, src);
+            long long p;
+            const bool valid = wave_pixel(a, w, src, p);
+            if (lp == 0 && valid) {
+                out[p] = m;
+                out[a.LL + p] = R0[b][q];
+                out[2 * a.LL + p] = R1[b][q];
+                out[3 * a.LL + p] = R2[b][q];
+                out[4 * a.LL + p] = anc_hb[b][q];
+                out[5 * a.LL + p] = anc_ox[b][q];
             }
         }
-        const float chb = T[0], cox = T[1];
-#pragma unroll
-        for (int j = 0; j < PIX; ++j) {
-            kahan_add(s0[j], c0[j], t0s[j]);
-            kahan_add(s1[j], c1[j], fmaf(chb - ahb[j], t0s[j], t1s[j]));
-            kahan_add(s2[j], c2[j], fmaf(cox - aox[j], t0s[j], t2s[j]));
-        }
-    }
+}
 
-    float *out = a.part + ((size_t)f * S + split) * kPartFields * a.LL;
+// Direct kernel: one LL pixel per lane, logits in the difference form
+// t - m = -(r - v_g)^2 - m on the VALU with wave-uniform (scalar) node loads.
+__global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArgs a) {
+    constexpr int PW = 64;
+    const int lane = threadIdx.x & 63;
+    const WaveWork w = wave_work<PW>(a);
+    const float *zf = a.z + (size_t)w.f * 6 * a.LL;
+    long long p;
+    const bool valid = wave_pixel(a, w, lane, p);
+    float ph[3], pl[3];
 #pragma unroll
-    for (int j = 0; j < PIX; ++j) {
-        const long long p = base + (long long)j * kBlockThreads;
-        if (p < a.LL) {
-            out[p] = -nref[j];
-            out[a.LL + p] = s0[j];
-            out[2 * a.LL + p] = s1[j];
-            out[3 * a.LL + p] = s2[j];
-            out[4 * a.LL + p] = ahb[j];
-            out[5 * a.LL + p] = aox[j];
+    for (int k = 0; k < 3; ++k) load_obs(zf, a.LL, p, k, a.scale, ph[k], pl[k]);
+    const PixelRef ref = pixel_reference<PW, 1>(a, w, ph, pl, 0);
+    const float nm = -ref.m;
+    float R0 = 0.f, R1 = 0.f, R2 = 0.f, K0 = 0.f, K1 = 0.f, K2 = 0.f;
+    for (int si = w.s0; si < w.s1; ++si) {
+        const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+        float r[3];
+        recentre(T, ph, pl, r);
+        float L0 = 0.f, L1 = 0.f, L2 = 0.f;
+        const float *__restrict__ C = T + kSupHdr + kMaxProbes * kProbeFloats;
+        for (int c = 0; c < a.chunks_per_super; ++c, C += kChunkFloats) {
+#pragma unroll
+            for (int j = 0; j < kChunkNodes; ++j) {
+                const float d0 = r[0] - C[j], d1 = r[1] - C[16 + j], d2 = r[2] - C[32 + j];
+                float t = fmaf(-d0, d0, nm);
+                t = fmaf(-d1, d1, t);
+                t = fmaf(-d2, d2, t);
+                const float wt = __builtin_amdgcn_exp2f(t);
+                L0 += wt;
+                L1 = fmaf(wt, C[64 + j], L1);
+                L2 = fmaf(wt, C[80 + j], L2);
+            }
         }
+        kahan_add(R0, K0, L0);
+        kahan_add(R1, K1, fmaf(T[6] - ref.ahb, L0, L1));
+        kahan_add(R2, K2, fmaf(T[7] - ref.aox, L0, L2));
+    }
+    if (valid) {
+        float *out = a.part + ((size_t)w.f * a.split + w.split) * kPartFields * a.LL;
+        out[p] = ref.m;
+        out[a.LL + p] = R0;
+        out[2 * a.LL + p] = R1;
+        out[3 * a.LL + p] = R2;
+        out[4 * a.LL + p] = ref.ahb;
+        out[5 * a.LL + p] = ref.aox;
     }
 }
 
@@ -493,12 +704,15 @@ hipError_t launch_log_haar(const void *frames, int n_frames, const HaarArgs &a, 
     return hipGetLastError();
 }
 
-hipError_t launch_posterior(const PosteriorArgs &a, hipStream_t s) {
-    const long long per_block = (long long)kBlockThreads * kPosteriorPix;
-    const long long chunks = (a.LL + per_block - 1) / per_block;
-    const long long grid = chunks * a.n_frames * a.split;
+hipError_t launch_posterior(const PosteriorArgs &a, bool mfma, hipStream_t s) {
+    const int th = (mfma ? 16 * kPixelBlocks : 64) / kWaveTileW;
+    const long long per_frame = (long long)((a.wl + kWaveTileW - 1) / kWaveTileW) * ((a.hl + 4 * th - 1) / (4 * th));
+    const long long grid = per_frame * a.n_frames * a.split;
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_posterior<kPosteriorPix>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
+    if (mfma)
+        hipLaunchKernelGGL(k_posterior<kPixelBlocks>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_posterior_direct, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -27,7 +27,10 @@ struct hb_plan_s {
     int device = 0;
     Dims dims{};
     int split = 1;
-    int n_tiles = 0;
+    int side = 8;
+    double radius = 0;        // largest super-tile radius, scaled units
+    bool use_mfma = true;
+    int n_tiles = 0;      // super-tiles
     long long n_nodes = 0;
     bool has_model = false;
 
@@ -35,12 +38,14 @@ struct hb_plan_s {
     double *d_k0 = nullptr;   // K0 inputs followed by outputs
     size_t k0_in = 0;         // doubles of K0 input
     float *d_mf = nullptr;    // FP32 M (6) + low-pass Tikhonov offset (2)
-    float *d_tiles = nullptr;
+    float *d_tiles = nullptr;   // super-tile table
     float *d_z = nullptr;
     float2 *d_det = nullptr;
     float *d_part = nullptr;
     float2 *d_est = nullptr;
+    unsigned long long *d_work = nullptr;  // posterior pairs evaluated while timing
     size_t bytes = 0;
+    long long full_pairs = 0;              // algorithmic pairs of the timed calls
 
     hb_plan_info_t info{};
     float iref[3] = {1, 1, 1};
@@ -98,10 +103,11 @@ Dims make_dims(const hb_plan_desc_t &d) {
     return m;
 }
 
-int auto_split(const Dims &dm, int n_tiles) {
-    // Aim for about four waves per SIMD (1024 SIMDs) from a single frame.
-    const long long lanes = (dm.LL + kPosteriorPix - 1) / kPosteriorPix;
-    const long long waves = std::max(1LL, (lanes + 63) / 64);
+int auto_split(const Dims &dm, int n_tiles, int max_batch) {
+    // Aim for about four waves per SIMD (1024 SIMDs) from a full batch.  The
+    // split is fixed per plan, so a frame gives the same bits in any batch.
+    const long long per_wave = 16LL * kPixelBlocks;
+    const long long waves = std::max(1LL, ((long long)max_batch * dm.LL + per_wave - 1) / per_wave);
     int s = 1;
     while (s < 64 && waves * s < 4096) s *= 2;
     return std::max(1, std::min(s, n_tiles));
@@ -125,6 +131,7 @@ void free_plan(hb_plan_s *p) {
     (void)hipFree(p->d_det);
     (void)hipFree(p->d_part);
     (void)hipFree(p->d_est);
+    (void)hipFree(p->d_work);
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
     delete p;
 }
@@ -153,89 +160,126 @@ struct ForwardModel {
     }
 };
 
-// Build the tiled, centred, scaled grid table (FP64 arithmetic, FP32 storage).
-void build_tiles(const hb_plan_desc_t &d, const ForwardModel &fm, const double mu_ref[3], double scale,
-                 std::vector<float> &tiles) {
+// Build the super-tile table (FP64 arithmetic, FP32 storage): scaled
+// log-attenuation of every grid node centred on mu_ref, stored relative to its
+// super-tile centre in the MFMA operand layout, plus moments, boxes and probes.
+double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const double mu_ref[3], double scale,
+                    int side, std::vector<float> &table) {
     const int GT = d.grid_thb, GS = d.grid_so2;
-    const int nta = (GT + kTileSide - 1) / kTileSide, nts = (GS + kTileSide - 1) / kTileSide;
-    const int n_tiles = nta * nts;
-    tiles.assign((size_t)n_tiles * kTileFloats, 0.0f);
-    auto work = [&](int t_begin, int t_end) {
-        for (int t = t_begin; t < t_end; ++t) {
-            const int ta = t / nts, ts = t % nts;
-            const int a0 = ta * kTileSide, b0 = ts * kTileSide;
-            const int na = std::min(kTileSide, GT - a0), nb = std::min(kTileSide, GS - b0);
-            float *T = &tiles[(size_t)t * kTileFloats];
-            float *N = T + kTileHdr;
-            double chb[kTileNodes], cox[kTileNodes];
-            double mhb = 0, mox = 0;
-            for (int i = 0; i < na; ++i)
-                for (int j = 0; j < nb; ++j) {
+    const int nsa = (GT + side - 1) / side, nss = (GS + side - 1) / side;
+    const int n_sup = nsa * nss;
+    const int stride = super_floats(side);
+    const int cps = side / 4;  // chunks per super-tile side
+    table.assign((size_t)n_sup * stride, 0.0f);
+    std::vector<double> radius(n_sup, 0.0);
+    auto work = [&](int s_begin, int s_end) {
+        std::vector<double> mu((size_t)side * side * 3), chb((size_t)side * side), cox((size_t)side * side);
+        std::vector<char> real((size_t)side * side);
+        for (int sidx = s_begin; sidx < s_end; ++sidx) {
+            const int sa = sidx / nss, ss = sidx % nss;
+            const int a0 = sa * side, b0 = ss * side;
+            float *T = &table[(size_t)sidx * stride];
+            // nodes of this super-tile
+            double cen[3] = {0, 0, 0}, mhb = 0, mox = 0;
+            int nreal = 0;
+            for (int i = 0; i < side; ++i)
+                for (int j = 0; j < side; ++j) {
+                    const int n = i * side + j;
+                    real[n] = (a0 + i < GT) && (b0 + j < GS);
+                    if (!real[n]) continue;
                     const double thb = lin(d.thb_min, d.thb_max, GT, a0 + i);
                     const double so2 = lin(d.so2_min, d.so2_max, GS, b0 + j);
-                    const int slot = i * kTileSide + j;
-                    chb[slot] = thb * (1.0 - so2);
-                    cox[slot] = thb * so2;
-                    mhb += chb[slot];
-                    mox += cox[slot];
-                }
-            const float centre_hb = (float)(mhb / (na * nb)), centre_ox = (float)(mox / (na * nb));
-            // Scaled, centred log-attenuation of the real nodes, and their mean.
-            double mu_s[kTileNodes][3];
-            double cen[3] = {0, 0, 0};
-            for (int i = 0; i < na; ++i)
-                for (int j = 0; j < nb; ++j) {
-                    const int slot = i * kTileSide + j;
+                    chb[n] = thb * (1.0 - so2);
+                    cox[n] = thb * so2;
                     double m[3];
-                    fm.mu(chb[slot], cox[slot], m);
+                    fm.mu(chb[n], cox[n], m);
                     for (int k = 0; k < 3; ++k) {
-                        mu_s[slot][k] = scale * (m[k] - mu_ref[k]);
-                        cen[k] += mu_s[slot][k];
+                        mu[3 * n + k] = scale * (m[k] - mu_ref[k]);
+                        cen[k] += mu[3 * n + k];
                     }
+                    mhb += chb[n];
+                    mox += cox[n];
+                    ++nreal;
                 }
             float cen_hi[3], cen_lo[3];
+            double cen_d[3];
             for (int k = 0; k < 3; ++k) {
-                const double c = cen[k] / (na * nb);
+                const double c = cen[k] / nreal;
                 cen_hi[k] = (float)c;
                 cen_lo[k] = (float)(c - (double)cen_hi[k]);
+                cen_d[k] = (double)cen_hi[k] + (double)cen_lo[k];
             }
-            float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-            for (int slot = 0; slot < kTileNodes; ++slot) {
-                const int i = slot / kTileSide, j = slot % kTileSide;
-                if (i >= na || j >= nb) {
-                    for (int k = 0; k < 3; ++k) N[k * kTileNodes + slot] = kPadCoord;
-                    N[3 * kTileNodes + slot] = 0.0f;
-                    N[4 * kTileNodes + slot] = 0.0f;
-                    continue;
+            const float chb_c = (float)(mhb / nreal), cox_c = (float)(mox / nreal);
+            auto rel = [&](int n, int k) { return mu[3 * n + k] - cen_d[k]; };
+            float blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            // chunks
+            for (int ca = 0; ca < cps; ++ca)
+                for (int cs = 0; cs < cps; ++cs) {
+                    float *C = T + kSupHdr + kMaxProbes * kProbeFloats + (size_t)(ca * cps + cs) * kChunkFloats;
+                    float clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+                    for (int j = 0; j < kChunkNodes; ++j) {
+                        const int n = (4 * ca + j / 4) * side + 4 * cs + j % 4;
+                        if (!real[n]) {
+                            C[j] = C[16 + j] = C[32 + j] = kPadCoord;
+                            C[48 + j] = kPadLogit;
+                            C[64 + j] = C[80 + j] = 0.0f;
+                            continue;
+                        }
+                        double sq = 0;
+                        for (int k = 0; k < 3; ++k) {
+                            const float v = (float)rel(n, k);
+                            C[16 * k + j] = v;
+                            sq += (double)v * (double)v;
+                            clo[k] = std::min(clo[k], v);
+                            chi[k] = std::max(chi[k], v);
+                        }
+                        C[48 + j] = (float)(-sq);
+                        radius[sidx] = std::max(radius[sidx], std::sqrt(sq));
+                        C[64 + j] = (float)(chb[n] - (double)chb_c);
+                        C[80 + j] = (float)(cox[n] - (double)cox_c);
+                    }
+                    for (int k = 0; k < 3; ++k) {
+                        C[96 + k] = clo[k];
+                        C[99 + k] = chi[k];
+                        blo[k] = std::min(blo[k], clo[k]);
+                        bhi[k] = std::max(bhi[k], chi[k]);
+                    }
                 }
-                for (int k = 0; k < 3; ++k) {
-                    const double c = (double)cen_hi[k] + (double)cen_lo[k];
-                    const float v = (float)(mu_s[slot][k] - c);
-                    N[k * kTileNodes + slot] = v;
-                    lo[k] = std::min(lo[k], v);
-                    hi[k] = std::max(hi[k], v);
+            // probes: the middle real node of each 8 x 8 patch
+            int np = 0;
+            for (int pa = 0; pa < side; pa += 8)
+                for (int pb = 0; pb < side; pb += 8) {
+                    const int na = std::min(std::min(8, side), GT - a0 - pa);
+                    const int nb = std::min(std::min(8, side), GS - b0 - pb);
+                    if (na <= 0 || nb <= 0) continue;
+                    const int n = (pa + (na - 1) / 2) * side + pb + (nb - 1) / 2;
+                    float *P = T + kSupHdr + np * kProbeFloats;
+                    for (int k = 0; k < 3; ++k) {
+                        // the probe must carry the same float coordinates as its node
+                        P[k] = (float)rel(n, k);
+                    }
+                    P[3] = (float)chb[n];
+                    P[4] = (float)cox[n];
+                    ++np;
                 }
-                N[3 * kTileNodes + slot] = (float)(chb[slot] - (double)centre_hb);
-                N[4 * kTileNodes + slot] = (float)(cox[slot] - (double)centre_ox);
-            }
-            T[0] = centre_hb;
-            T[1] = centre_ox;
             for (int k = 0; k < 3; ++k) {
-                T[2 + k] = lo[k];
-                T[5 + k] = hi[k];
-                T[9 + k] = cen_hi[k];
-                T[12 + k] = cen_lo[k];
+                T[k] = cen_hi[k];
+                T[3 + k] = cen_lo[k];
+                T[8 + k] = blo[k];
+                T[11 + k] = bhi[k];
             }
-            const int probe = ((na - 1) / 2) * kTileSide + (nb - 1) / 2;
-            std::memcpy(&T[8], &probe, sizeof(int));
+            T[6] = chb_c;
+            T[7] = cox_c;
+            std::memcpy(&T[14], &np, sizeof(int));
         }
     };
     unsigned nt = std::max(1u, std::min(std::thread::hardware_concurrency(), 32u));
-    nt = std::min<unsigned>(nt, (unsigned)n_tiles);
+    nt = std::min<unsigned>(nt, (unsigned)n_sup);
     std::vector<std::thread> th;
     for (unsigned i = 0; i < nt; ++i)
-        th.emplace_back(work, (int)((long long)n_tiles * i / nt), (int)((long long)n_tiles * (i + 1) / nt));
+        th.emplace_back(work, (int)((long long)n_sup * i / nt), (int)((long long)n_sup * (i + 1) / nt));
     for (auto &x : th) x.join();
+    return *std::max_element(radius.begin(), radius.end());
 }
 
 }  // namespace
@@ -299,22 +343,25 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     p->desc = *desc;
     p->device = device;
     p->dims = make_dims(*desc);
-    const int nta = (desc->grid_thb + kTileSide - 1) / kTileSide, nts = (desc->grid_so2 + kTileSide - 1) / kTileSide;
-    p->n_tiles = nta * nts;
+    p->side = super_side(desc->grid_thb, desc->grid_so2);
+    const int nsa = (desc->grid_thb + p->side - 1) / p->side, nss = (desc->grid_so2 + p->side - 1) / p->side;
+    p->n_tiles = nsa * nss;
     p->n_nodes = (long long)desc->grid_thb * desc->grid_so2;
-    p->split = desc->grid_split > 0 ? std::min(desc->grid_split, p->n_tiles) : auto_split(p->dims, p->n_tiles);
+    p->split = desc->grid_split > 0 ? std::min(desc->grid_split, p->n_tiles) : auto_split(p->dims, p->n_tiles, desc->max_batch);
 
     const size_t nb = (size_t)desc->max_batch;
     const size_t LL = (size_t)p->dims.LL;
     const size_t HW = (size_t)desc->height * desc->width;
     st = HB_OK;
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_mf, sizeof(float) * 8);
-    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_tiles, sizeof(float) * (size_t)p->n_tiles * kTileFloats);
+    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_tiles, sizeof(float) * (size_t)p->n_tiles * super_floats(p->side));
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_z, sizeof(float) * nb * 6 * LL);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_det, sizeof(float2) * nb * HW);
     if (st == HB_OK && desc->lowpass == HB_LOWPASS_BAYES)
         st = dev_alloc(p, (void **)&p->d_part, sizeof(float) * nb * p->split * kPartFields * LL);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_est, sizeof(float2) * nb * LL);
+    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_work, sizeof(unsigned long long));
+    if (st == HB_OK && hipMemset(p->d_work, 0, sizeof(unsigned long long)) != hipSuccess) st = HB_ERR_DEVICE;
     if (st != HB_OK) {
         free_plan(p);
         return st;
@@ -407,7 +454,11 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
         return HB_ERR_DEVICE;
 
     std::vector<float> tiles;
-    build_tiles(d, model, r, (double)p->scale, tiles);
+    p->radius = build_supers(d, model, r, (double)p->scale, p->side, tiles);
+    const double h_thb = d.grid_thb > 1 ? (d.thb_max - d.thb_min) / (d.grid_thb - 1) : 0.0;
+    const double h_so2 = d.grid_so2 > 1 ? d.thb_max * (d.so2_max - d.so2_min) / (d.grid_so2 - 1) : 0.0;
+    p->use_mfma = p->radius * p->radius * std::max(h_thb, h_so2) <= kMfmaPrecisionBudget;
+    p->info.posterior_kernel = p->use_mfma ? 0 : 1;
     if (hipMemcpy(p->d_tiles, tiles.data(), sizeof(float) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
         return HB_ERR_DEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return HB_ERR_DEVICE;
@@ -463,14 +514,20 @@ hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_fram
     if (p->desc.lowpass == HB_LOWPASS_BAYES) {
         PosteriorArgs pa{};
         pa.LL = p->dims.LL;
+        pa.hl = p->dims.hl;
+        pa.wl = p->dims.wl;
         pa.n_frames = n_frames;
         pa.z = p->d_z;
-        pa.tiles = p->d_tiles;
-        pa.n_tiles = p->n_tiles;
+        pa.supers = p->d_tiles;
+        pa.n_supers = p->n_tiles;
+        pa.super_stride = super_floats(p->side);
+        pa.chunks_per_super = (p->side / 4) * (p->side / 4);
         pa.split = p->split;
         pa.scale = p->scale;
         pa.part = p->d_part;
-        if (launch_posterior(pa, s) != hipSuccess) return HB_ERR_DEVICE;
+        pa.work = ev ? p->d_work : nullptr;
+        if (ev) p->full_pairs += (long long)n_frames * p->dims.LL * p->n_nodes;
+        if (launch_posterior(pa, p->use_mfma, s) != hipSuccess) return HB_ERR_DEVICE;
     }
     if (mark(2) != hipSuccess) return HB_ERR_DEVICE;
     RecomposeArgs ra{};
@@ -512,8 +569,23 @@ hb_status_t hb_plan_get_info(hb_plan_t p, hb_plan_info_t *info) {
 
 hb_status_t hb_plan_set_timing(hb_plan_t p, int32_t enable) {
     if (!p) return HB_ERR_INVALID_ARG;
+    if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return HB_ERR_DEVICE;
+    if (hipMemset(p->d_work, 0, sizeof(unsigned long long)) != hipSuccess) return HB_ERR_DEVICE;
+    p->full_pairs = 0;
     p->timing = enable != 0;
     p->timed_calls = 0;
+    return HB_OK;
+}
+
+hb_status_t hb_plan_get_work(hb_plan_t p, int64_t *evaluated, int64_t *full) {
+    if (!p || !evaluated || !full) return HB_ERR_INVALID_ARG;
+    if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
+    unsigned long long v = 0;
+    if (hipDeviceSynchronize() != hipSuccess) return HB_ERR_DEVICE;
+    if (hipMemcpy(&v, p->d_work, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return HB_ERR_DEVICE;
+    *evaluated = (int64_t)v;
+    *full = p->full_pairs;
     return HB_OK;
 }
 

@@ -73,7 +73,8 @@ class hb_plan_info_t(ctypes.Structure):
     _fields_ = [("E", ctypes.c_double * 6), ("M", ctypes.c_double * 6), ("gamma", ctypes.c_double),
                 ("ref_hb", ctypes.c_double), ("ref_hbo2", ctypes.c_double),
                 ("mu_ref", ctypes.c_double * 3), ("grid_split", ctypes.c_int32),
-                ("n_tiles", ctypes.c_int32), ("n_nodes", ctypes.c_int64)]
+                ("n_tiles", ctypes.c_int32), ("posterior_kernel", ctypes.c_int32),
+                ("n_nodes", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -91,13 +92,15 @@ _lib.hb_plan_get_info.argtypes = [_P, ctypes.POINTER(hb_plan_info_t)]
 _lib.hb_plan_set_timing.argtypes = [_P, ctypes.c_int32]
 _lib.hb_plan_get_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 _lib.hb_debug_copy.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]
+_lib.hb_plan_get_work.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
 for _f in ("hb_plan_desc_default", "hb_plan_create", "hb_set_forward_model", "hb_estimate_frames",
-           "hb_destroy", "hb_plan_get_info", "hb_plan_set_timing", "hb_plan_get_timing", "hb_debug_copy"):
+           "hb_destroy", "hb_plan_get_info", "hb_plan_set_timing", "hb_plan_get_timing", "hb_debug_copy",
+           "hb_plan_get_work"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("hb_plan_desc_default", "hb_plan_create", "hb_set_forward_model", "hb_estimate_frames",
             "hb_destroy", "hb_status_string", "hb_plan_device_bytes", "hb_plan_get_info",
-            "hb_plan_set_timing", "hb_plan_get_timing", "hb_debug_copy")
+            "hb_plan_set_timing", "hb_plan_get_timing", "hb_debug_copy", "hb_plan_get_work")
 
 
 class HbError(RuntimeError):
@@ -163,7 +166,8 @@ def hb_plan_get_info(plan: int) -> Dict[str, object]:
     _check(_lib.hb_plan_get_info(_P(plan), ctypes.byref(info)), "hb_plan_get_info")
     return dict(E=np.array(info.E[:]).reshape(3, 2), M=np.array(info.M[:]).reshape(2, 3),
                 gamma=info.gamma, ref=(info.ref_hb, info.ref_hbo2), mu_ref=np.array(info.mu_ref[:]),
-                grid_split=info.grid_split, n_tiles=info.n_tiles, n_nodes=info.n_nodes)
+                grid_split=info.grid_split, n_tiles=info.n_tiles, n_nodes=info.n_nodes,
+                posterior_kernel=("mfma", "direct")[info.posterior_kernel])
 
 
 def hb_plan_set_timing(plan: int, enable: bool) -> None:
@@ -175,6 +179,13 @@ def hb_plan_get_timing(plan: int) -> Tuple[np.ndarray, np.ndarray]:
     n = (ctypes.c_int64 * 4)()
     _check(_lib.hb_plan_get_timing(_P(plan), ms, n), "hb_plan_get_timing")
     return np.array(ms[:]), np.array(n[:])
+
+
+def hb_plan_get_work(plan: int) -> Tuple[int, int]:
+    ev = ctypes.c_int64()
+    full = ctypes.c_int64()
+    _check(_lib.hb_plan_get_work(_P(plan), ctypes.byref(ev), ctypes.byref(full)), "hb_plan_get_work")
+    return ev.value, full.value
 
 
 def hb_debug_copy(plan: int, which: int, frame: int, out: np.ndarray) -> np.ndarray:

@@ -53,7 +53,7 @@ int main(void) {
   F(hb_plan_desc_t, thb_min) F(hb_plan_desc_t, lambda) F(hb_plan_desc_t, ref_thb)
   F(hb_plan_desc_t, lowpass) F(hb_plan_desc_t, grid_split)
   F(hb_forward_model_t, eps_hb) F(hb_forward_model_t, path_length_cm)
-  F(hb_plan_info_t, gamma) F(hb_plan_info_t, grid_split) F(hb_plan_info_t, n_nodes)
+  F(hb_plan_info_t, gamma) F(hb_plan_info_t, grid_split) F(hb_plan_info_t, posterior_kernel) F(hb_plan_info_t, n_nodes)
   return 0;
 }
 """)
@@ -131,6 +131,7 @@ def test_null_arguments(hb):
     assert lib.hb_plan_set_timing(None, 1) == hb.HB_ERR_INVALID_ARG
     assert lib.hb_plan_get_info(None, None) == hb.HB_ERR_INVALID_ARG
     assert lib.hb_debug_copy(None, 0, 0, None, 0) == hb.HB_ERR_INVALID_ARG
+    assert lib.hb_plan_get_work(None, None, None) == hb.HB_ERR_INVALID_ARG
 
 
 def test_library_has_no_cpu_fallback_symbols(hb):

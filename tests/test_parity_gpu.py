@@ -207,3 +207,45 @@ def test_null_maps_are_skipped(torch_cuda):
     assert np.all(np.isnan(part[:, 0])) and np.all(np.isnan(part[:, 2]))
     assert np.array_equal(part[:, 1], full[:, 1]) and np.array_equal(part[:, 3], full[:, 3], equal_nan=True)
     run.close()
+
+
+@pytest.mark.parametrize("grid,sigma,kernel", [(256, 0.01, "mfma"), (128, 0.01, "mfma"), (512, 0.01, "mfma"),
+                                               (64, 0.01, "mfma"), (32, 0.01, "mfma"), (16, 0.01, "direct"),
+                                               (48, 0.001, "direct")])
+def test_posterior_kernel_choice(torch_cuda, grid, sigma, kernel):
+    """Fine grids take the MFMA kernel, grids too coarse for its expanded
+    logit take the direct one (both are covered by the parity tests above)."""
+    from paper_1706_07263_amd import hb
+    d = hb.make_desc(64, 64, grid_thb=grid, grid_so2=grid, sigma=sigma)
+    with hb.Plan(d, 0) as p:
+        p.set_forward_model(synth.spectra())
+        assert p.info()["posterior_kernel"] == kernel
+
+
+@pytest.mark.parametrize("grid", [24, 32, 40])
+def test_parity_near_the_kernel_threshold(torch_cuda, grid):
+    w = synth.config1()
+    s = _settings(grid=grid)
+    run = hbtest.GpuRun(64, 64, s)
+    gpu = run(w.frames)
+    err = hbtest.assert_maps_close(gpu, hbtest.run_oracle(w.frames, "f32", s), f"G{grid}")
+    print(f"G{grid}", run.plan.info()["posterior_kernel"], err)
+    run.close()
+
+
+def test_exact_skipping_keeps_parity(torch_cuda):
+    """On a 256x256 grid most chunks carry weights that are exactly zero; the
+    kernel skips them (fewer evaluated pairs) and still matches the oracle."""
+    from paper_1706_07263_amd import hb
+    fr, _, _ = synth.single_frame(128, 192, config=64)
+    s = _settings(levels=2, grid=256)
+    run = hbtest.GpuRun(192, 128, s)
+    hb.hb_plan_set_timing(run.plan.handle, True)
+    gpu = run(fr[None])
+    evaluated, full = hb.hb_plan_get_work(run.plan.handle)
+    hb.hb_plan_set_timing(run.plan.handle, False)
+    assert full == 32 * 48 * 256 * 256
+    assert 0 < evaluated < full
+    print("evaluated fraction", evaluated / full)
+    hbtest.assert_maps_close(gpu, hbtest.run_oracle(fr[None], "f32", s), "skipping")
+    run.close()
