@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample (0 = skip)")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="duration of the 16-stream serving run (0 = skip)")
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=48.0)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -81,6 +85,35 @@ def cpu_baseline(target_s: float, levels: int, grid: int, quiet: bool):
             "sample": f"rows 0..{rows - 1} of frame 0 (1920x{rows} px, "
                       f"{(rows // b) * (1920 // b)} low-pass pixels x {grid * grid} nodes), "
                       f"{dt:.2f} s, scaled by {rows}/1080"}
+
+
+SERVE_MAX_BATCH = {(480, 640): 8, (1024, 1280): 6, (1080, 1920): 4, (2160, 3840): 2}
+
+
+def serving(a):
+    """16 Poisson camera streams of mixed resolution at 30 fps, FP16 frames."""
+    import torch
+    from paper_1706_07263_amd import synth
+    from paper_1706_07263_amd.serve import GpuExecutor, Server, render_sources, workload_requests
+    reqs, offered = workload_requests(a.serve_warmup + a.serve_seconds)
+    classes = sorted(offered, key=lambda c: c.pixels)
+    log(f"serving: rendering {len(classes)} source frames", a.quiet)
+    raw = render_sources(classes, n_sources=1, workers=8)
+    sources = {c: torch.from_numpy(v).pin_memory() for c, v in raw.items()}
+    ex = GpuExecutor(synth.spectra(), sources)
+    srv = Server(ex, {c: SERVE_MAX_BATCH[(c.height, c.width)] for c in classes},
+                 hbm_budget=int(a.serve_budget_gib * (1 << 30)), offered=offered, max_lanes=2)
+    log(f"serving: {len(srv.lanes)} lanes, {srv.used / 2**30:.2f} GiB; {len(reqs)} frames over "
+        f"{a.serve_warmup + a.serve_seconds:.1f} s", a.quiet)
+    rep = srv.run(reqs, warmup_s=a.serve_warmup)
+    srv.close()
+    out = rep.summary()
+    out["streams"] = 16
+    out["offered_pairs_per_s"] = sum(offered.values())
+    out["offered_mpixel_per_s"] = round(sum(r.cls.pixels for r in reqs) / (a.serve_warmup + a.serve_seconds) / 1e6, 1)
+    out["window_s"] = a.serve_seconds
+    log(f"serving: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, {out['mpixel_per_s']} Mpixel/s", a.quiet)
+    return out
 
 
 def main():
@@ -162,6 +195,11 @@ def main():
     hbm_bytes = B * H * W * (12 if a.dtype == "f32" else 6) + B * H * W * 16
     stage["log_haar_plus_recompose_GBps"] = hbm_bytes / ((stage["log_haar_ms"] + stage["recompose_ms"]) * 1e-3) / 1e9
 
+    plan.close()
+    del frames, maps
+    torch.cuda.empty_cache()
+    serve = serving(a) if a.serve_seconds > 0 else None
+
     cpu = None
     if a.cpu_seconds > 0:
         cpu = cpu_baseline(a.cpu_seconds, a.levels, a.grid, a.quiet)
@@ -180,9 +218,10 @@ def main():
         "stages_ms_per_call": {k: round(v, 4) for k, v in stage.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "p99_latency_ms_16_streams": serve["p99_ms"] if serve else None,
+        "serving": serve,
     }
     print(json.dumps(out), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":
