@@ -75,6 +75,28 @@ __device__ __forceinline__ float load_px(const uint16_t *p, size_t i) {
     return __uint_as_float((uint32_t)p[i] << 16);  // bfloat16 -> float32 is exact
 }
 
+__device__ __forceinline__ void load4(const float *p, float v[4]) {
+    const float4 x = *reinterpret_cast<const float4 *>(p);
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = x.z;
+    v[3] = x.w;
+}
+__device__ __forceinline__ void load4(const __half *p, float v[4]) {
+    const uint2 x = *reinterpret_cast<const uint2 *>(p);
+    v[0] = __half2float(__ushort_as_half((unsigned short)(x.x & 0xffffu)));
+    v[1] = __half2float(__ushort_as_half((unsigned short)(x.x >> 16)));
+    v[2] = __half2float(__ushort_as_half((unsigned short)(x.y & 0xffffu)));
+    v[3] = __half2float(__ushort_as_half((unsigned short)(x.y >> 16)));
+}
+__device__ __forceinline__ void load4(const uint16_t *p, float v[4]) {
+    const uint2 x = *reinterpret_cast<const uint2 *>(p);
+    v[0] = __uint_as_float(x.x << 16);
+    v[1] = __uint_as_float(x.x & 0xffff0000u);
+    v[2] = __uint_as_float(x.y << 16);
+    v[3] = __uint_as_float(x.y & 0xffff0000u);
+}
+
 struct StripPos {
     int f, br, blk0, nb, ncols, Wt, row0, col0, B;
 };
@@ -116,90 +138,119 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
     const int n = d.levels, B = s.B, Wt = s.Wt, ncols = s.ncols;
     const int tid = threadIdx.x;
 
-    // 1. Coalesced load of the strip (rows are contiguous HWC runs), clamp.
+    // 1. Coalesced load of the strip, clamp.  Each row of the strip is one
+    //    contiguous HWC run of ncols * 3 values; with 4-value alignment the
+    //    loads are 16-byte (FP32) or 8-byte (FP16/BF16) vectors, all issued
+    //    before any is used.
     const size_t frame_off = (size_t)s.f * d.H * d.W * 3;
     const int run = ncols * 3;
-    for (int i = tid; i < B * run; i += kBlockThreads) {
-        const int r = i / run, rem = i - r * run, c = rem / 3, k = rem - 3 * c;
-        float v = load_px(frames, frame_off + ((size_t)(s.row0 + r) * d.W + s.col0) * 3 + rem);
+    const T *__restrict__ base = frames + frame_off + ((size_t)s.row0 * d.W + s.col0) * 3;
+    const size_t row_stride = (size_t)d.W * 3;
+    auto put = [&](int r, int p, float v) {
+        const int c = p / 3, k = p - 3 * c;
         v = (v < a.floor) ? a.floor : v;  // NaN stays NaN
         s_i[k][r * Wt + c] = v;
         s_u[k][r * Wt + c] = v;
+    };
+    if ((d.W & 3) == 0 && (run & 3) == 0) {
+        const int r4 = run >> 2, total = B * r4;
+        constexpr int kMaxVec = kStripPixels * 3 / 4 / kBlockThreads;   // 6
+        float v[kMaxVec][4];
+        int rr[kMaxVec], jj[kMaxVec];
+#pragma unroll
+        for (int t = 0; t < kMaxVec; ++t) {
+            const int idx = tid + t * kBlockThreads;
+            rr[t] = idx < total ? idx / r4 : 0;
+            jj[t] = idx < total ? idx - rr[t] * r4 : -1;
+            if (jj[t] >= 0) load4(base + rr[t] * row_stride + 4 * jj[t], v[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < kMaxVec; ++t)
+            if (jj[t] >= 0)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) put(rr[t], 4 * jj[t] + e, v[t][e]);
+    } else {
+        for (int r = 0; r < B; ++r)
+            for (int p = tid; p < run; p += kBlockThreads) put(r, p, load_px(base, r * row_stride + p));
     }
     __syncthreads();
 
     // 2. Block sums of intensity by a 2x2 cascade, then the block mean R.
     for (int l = 1; l <= n; ++l) {
-        const int h = 1 << (l - 1), g2 = 2 * h, gr = B / g2, gc = ncols / g2;
-        for (int i = tid; i < gr * gc * 3; i += kBlockThreads) {
-            const int k = i % 3, q = i / 3, r = (q / gc) * g2, c = (q % gc) * g2;
-            float *u = s_u[k];
-            u[r * Wt + c] = (u[r * Wt + c] + u[r * Wt + c + h]) + (u[(r + h) * Wt + c] + u[(r + h) * Wt + c + h]);
-        }
+        const int h = 1 << (l - 1), g2 = 2 * h, gc = ncols >> l;
+        for (int r = 0; r < B; r += g2)
+            for (int q = tid; q < gc * 3; q += kBlockThreads) {
+                const int cg = q / 3, k = q - 3 * cg, c = cg * g2;
+                float *u = s_u[k];
+                u[r * Wt + c] = (u[r * Wt + c] + u[r * Wt + c + h]) + (u[(r + h) * Wt + c] + u[(r + h) * Wt + c + h]);
+            }
         __syncthreads();
     }
     if (n > 0) {
         const float inv = 1.0f / (float)(1 << (2 * n));
-        for (int i = tid; i < s.nb * 3; i += kBlockThreads) {
-            const int k = i % 3, j = i / 3;
+        for (int q = tid; q < s.nb * 3; q += kBlockThreads) {
+            const int j = q / 3, k = q - 3 * j;
             s_r[k][j] = s_u[k][j << n] * inv;
         }
     }
     __syncthreads();
 
     // 3. Log-ratio to the block reference.
-    for (int i = tid; i < B * ncols * 3; i += kBlockThreads) {
-        const int k = i % 3, q = i / 3, r = q / ncols, c = q - r * ncols;
-        const float I = s_i[k][r * Wt + c];
-        const float R = (n > 0) ? s_r[k][c >> n] : I;
-        s_u[k][r * Wt + c] = -log1pf((I - R) / R);
-    }
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            for (int c = tid; c < ncols; c += kBlockThreads) {
+                const float I = s_i[k][r * Wt + c];
+                const float R = (n > 0) ? s_r[k][c >> n] : I;
+                s_u[k][r * Wt + c] = -log1pf((I - R) / R);
+            }
     __syncthreads();
 
     // 4. n-level Haar in place.  Window (a, b, c, d) = (r,c), (r,c+h), (r+h,c),
     //    (r+h,c+h); coefficients = window * H (Eq. 1-2): LL -> (r,c),
     //    row difference -> (r+h,c), diagonal -> (r+h,c+h), column difference -> (r,c+h).
     for (int l = 1; l <= n; ++l) {
-        const int h = 1 << (l - 1), g2 = 2 * h, gr = B / g2, gc = ncols / g2;
-        for (int i = tid; i < gr * gc * 3; i += kBlockThreads) {
-            const int k = i % 3, q = i / 3, r = (q / gc) * g2, c = (q % gc) * g2;
-            float *u = s_u[k];
-            const float w0 = u[r * Wt + c], w1 = u[r * Wt + c + h];
-            const float w2 = u[(r + h) * Wt + c], w3 = u[(r + h) * Wt + c + h];
-            u[r * Wt + c] = 0.5f * ((w0 + w1) + (w2 + w3));
-            u[(r + h) * Wt + c] = 0.5f * ((w0 + w1) - (w2 + w3));
-            u[(r + h) * Wt + c + h] = 0.5f * ((w0 - w1) - (w2 - w3));
-            u[r * Wt + c + h] = 0.5f * ((w0 - w1) + (w2 - w3));
-        }
+        const int h = 1 << (l - 1), g2 = 2 * h, gc = ncols >> l;
+        for (int r = 0; r < B; r += g2)
+            for (int q = tid; q < gc * 3; q += kBlockThreads) {
+                const int cg = q / 3, k = q - 3 * cg, c = cg * g2;
+                float *u = s_u[k];
+                const float w0 = u[r * Wt + c], w1 = u[r * Wt + c + h];
+                const float w2 = u[(r + h) * Wt + c], w3 = u[(r + h) * Wt + c + h];
+                u[r * Wt + c] = 0.5f * ((w0 + w1) + (w2 + w3));
+                u[(r + h) * Wt + c] = 0.5f * ((w0 + w1) - (w2 + w3));
+                u[(r + h) * Wt + c + h] = 0.5f * ((w0 - w1) - (w2 - w3));
+                u[r * Wt + c + h] = 0.5f * ((w0 - w1) + (w2 - w3));
+            }
         __syncthreads();
     }
 
     // 5. Centred low-pass observation z = ybar - mu_ref per block, as a
     //    double-float: ybar - mu_ref = ln(I_ref / R) + mean(u).
     const float invB = 1.0f / (float)B;
-    for (int i = tid; i < s.nb * 3; i += kBlockThreads) {
-        const int k = i % 3, j = i / 3;
+    for (int q = tid; q < s.nb * 3; q += kBlockThreads) {
+        const int j = q / 3, k = q - 3 * j;
         const float R = (n > 0) ? s_r[k][j] : s_i[k][j];
         float zh, zl;
         ln_ratio_df(a.iref[k], R, zh, zl);
         df_add(zh, zl, s_u[k][j << n] * invB);
-        const size_t q = (size_t)s.br * d.wl + s.blk0 + j;
-        a.z[((size_t)s.f * 6 + k) * d.LL + q] = zh;
-        a.z[((size_t)s.f * 6 + 3 + k) * d.LL + q] = zl;
+        const size_t o = (size_t)s.br * d.wl + s.blk0 + j;
+        a.z[((size_t)s.f * 6 + k) * d.LL + o] = zh;
+        a.z[((size_t)s.f * 6 + 3 + k) * d.LL + o] = zl;
     }
 
     // 6. Tikhonov on every directional coefficient: (Hb, HbO2) = M * (R, G, B).
     const float m0 = a.M[0], m1 = a.M[1], m2 = a.M[2], m3 = a.M[3], m4 = a.M[4], m5 = a.M[5];
-    for (int i = tid; i < B * ncols; i += kBlockThreads) {
-        const int r = i / ncols, c = i - r * ncols;
-        float2 o = make_float2(0.0f, 0.0f);
-        if (((r | c) & (B - 1)) != 0) {
-            const float d0 = s_u[0][r * Wt + c], d1 = s_u[1][r * Wt + c], d2 = s_u[2][r * Wt + c];
-            o.x = fmaf(m0, d0, fmaf(m1, d1, m2 * d2));
-            o.y = fmaf(m3, d0, fmaf(m4, d1, m5 * d2));
+    for (int r = 0; r < B; ++r)
+        for (int c = tid; c < ncols; c += kBlockThreads) {
+            float2 o = make_float2(0.0f, 0.0f);
+            if (((r | c) & (B - 1)) != 0) {
+                const float d0 = s_u[0][r * Wt + c], d1 = s_u[1][r * Wt + c], d2 = s_u[2][r * Wt + c];
+                o.x = fmaf(m0, d0, fmaf(m1, d1, m2 * d2));
+                o.y = fmaf(m3, d0, fmaf(m4, d1, m5 * d2));
+            }
+            a.det[((size_t)s.f * d.H + s.row0 + r) * d.W + s.col0 + c] = o;
         }
-        a.det[((size_t)s.f * d.H + s.row0 + r) * d.W + s.col0 + c] = o;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -475,13 +526,27 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
             const bool keep = cg + lane < a.chunks_per_super &&
                               box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > -kSkipLog2;
             unsigned long long mask = __ballot(keep);
-            while (mask) {
-                const int c = cg + __builtin_ctzll(mask);
+            if (mask == 0) continue;
+            // Walk the kept chunks with two operand buffers: the next chunk's
+            // operands are in flight while the current one is evaluated.
+            // The loads are issued unconditionally (the last chunk is simply
+            // loaded again), so the wait counts match on every path and a
+            // wait for the current chunk never waits for the next one.
+            int last = cg;
+            auto take = [&](float &bv, float &mh, float &mo) -> bool {
+                const bool got = mask != 0;
+                last = got ? cg + __builtin_ctzll(mask | (1ull << 63)) : last;
                 mask &= mask - 1;
-                const float *__restrict__ C = C0 + (size_t)c * kChunkFloats;
+                const float *__restrict__ C = C0 + (size_t)last * kChunkFloats;
+                bv = C[lane];
+                mh = C[64 + lp];
+                mo = C[80 + lp];
+                // keep these loads ahead of the evaluation that follows
+                __builtin_amdgcn_sched_barrier(0);
+                return got;
+            };
+            auto eval = [&](float bv, float mh, float mo) {
                 ++executed;
-                const float bv = C[lane];
-                const float mh = C[64 + lp], mo = C[80 + lp];
 #pragma unroll
                 for (int b = 0; b < PB; ++b) {
                     const f32x4 d = mfma_16x16x4(av[b], bv, cv[b]);
@@ -493,6 +558,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
                         L2[b][q] = fmaf(wt, mo, L2[b][q]);
                     }
                 }
+            };
+            float bA, mhA, moA, bB, mhB, moB;
+            take(bA, mhA, moA);
+            while (true) {
+                const bool gotB = take(bB, mhB, moB);
+                eval(bA, mhA, moA);
+                if (!gotB) break;
+                const bool gotA = take(bA, mhA, moA);
+                eval(bB, mhB, moB);
+                if (!gotA) break;
             }
         }
         const float chb = T[6], cox = T[7];
@@ -640,19 +715,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_recompose(RecomposeArgs a) {
         s_e[1][j] = e.y;
         a.est[(size_t)s.f * d.LL + q] = e;
     }
-    for (int i = tid; i < B * ncols; i += kBlockThreads) {
-        const int r = i / ncols, c = i - r * ncols;
-        const float2 v = a.det[((size_t)s.f * d.H + s.row0 + r) * d.W + s.col0 + c];
-        s_c[0][r * Wt + c] = v.x;
-        s_c[1][r * Wt + c] = v.y;
-    }
+    for (int r = 0; r < B; ++r)
+        for (int c = tid; c < ncols; c += kBlockThreads) {
+            const float2 v = a.det[((size_t)s.f * d.H + s.row0 + r) * d.W + s.col0 + c];
+            s_c[0][r * Wt + c] = v.x;
+            s_c[1][r * Wt + c] = v.y;
+        }
     __syncthreads();
 
     // Inverse Haar (Eq. 4): window = coefficients * H, levels n..1.
     for (int l = n; l >= 1; --l) {
-        const int h = 1 << (l - 1), g2 = 2 * h, gr = B / g2, gc = ncols / g2;
-        for (int i = tid; i < gr * gc * 2; i += kBlockThreads) {
-            const int k = i & 1, q = i >> 1, r = (q / gc) * g2, c = (q % gc) * g2;
+        const int h = 1 << (l - 1), g2 = 2 * h, gc = ncols >> l;
+        for (int r = 0; r < B; r += g2)
+        for (int q = tid; q < gc * 2; q += kBlockThreads) {
+            const int k = q & 1, c = (q >> 1) * g2;
             float *u = s_c[k];
             const float ll = u[r * Wt + c], d1 = u[(r + h) * Wt + c];
             const float d2 = u[(r + h) * Wt + c + h], d3 = u[r * Wt + c + h];
@@ -664,8 +740,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_recompose(RecomposeArgs a) {
         __syncthreads();
     }
 
-    for (int i = tid; i < B * ncols; i += kBlockThreads) {
-        const int r = i / ncols, c = i - r * ncols, j = c >> n;
+    for (int r = 0; r < B; ++r)
+    for (int c = tid; c < ncols; c += kBlockThreads) {
+        const int j = c >> n;
         const float hb = s_e[0][j] + s_c[0][r * Wt + c];
         const float hbo2 = s_e[1][j] + s_c[1][r * Wt + c];
         const float thb = hb + hbo2;
