@@ -29,6 +29,13 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # offset), 1 add + 2 mul + 2 add (three moments) = 15 flops, plus one exp.
 FLOPS_PER_PAIR = 15
 EXPS_PER_PAIR = 1
+# HBM bytes per posterior launch of the default workload (8 frames), from the
+# rocprofv3 FETCH_SIZE/WRITE_SIZE runs summarised in
+# profiles/hot_path_1080p_L2_G256_b8.md, valid for the kernel source whose
+# sha256 starts with KERNEL_SHA (reported as null for any other source or
+# workload).
+PROFILED_KERNEL_SHA = "62a59778f4f6d6fb"
+PROFILED_POSTERIOR_TRAFFIC = 143.1e6
 
 
 def parse():
@@ -183,9 +190,14 @@ def main():
     # skipped; the flops of the roofline are those actually executed).
     eval_per_launch = evaluated / max(launches[1], 1) if evaluated else pairs_per_launch
     achieved = eval_per_launch * FLOPS_PER_PAIR / k2_s / 1e12
+    import hashlib
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1706_07263_amd", "csrc", "hb_kernels.hip"), "rb")
+                         .read()).hexdigest()[:16]
+    default_workload = (B, a.levels, a.grid, a.dtype, a.split) == (8, 2, 256, "f32", 0)
+    traffic = PROFILED_POSTERIOR_TRAFFIC if (sha == PROFILED_KERNEL_SHA and default_workload) else None
     roofline = {"bound": "alu", "kernel": "k_posterior", "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": round(k2_s * 1e3, 4),
+                "traffic": traffic, "traffic_unit": "bytes per launch", "avg_launch_ms": round(k2_s * 1e3, 4),
                 "evaluated_pairs_per_launch": int(eval_per_launch), "full_grid_pairs_per_launch": pairs_per_launch,
                 "evaluated_pairs_per_s": eval_per_launch / k2_s,
                 "full_grid_pairs_per_s": pairs_per_launch / k2_s,
