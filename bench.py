@@ -55,6 +55,7 @@ def parse():
                     help="duration of the 16-stream serving run (0 = skip)")
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-budget-gib", type=float, default=48.0)
+    ap.add_argument("--no-table1", action="store_true", help="skip the Table 1 speed-ratio analogue")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -92,6 +93,47 @@ def cpu_baseline(target_s: float, levels: int, grid: int, quiet: bool):
             "sample": f"rows 0..{rows - 1} of frame 0 (1920x{rows} px, "
                       f"{(rows // b) * (1920 // b)} low-pass pixels x {grid * grid} nodes), "
                       f"{dt:.2f} s, scaled by {rows}/1080"}
+
+
+PAPER_TABLE1_HZ = {"bayes_full_resolution": 3.54, "proposed_w1": 12.7, "proposed_w3": 14.4, "tikhonov": 43.5}
+
+
+def time_plan(hb, torch, desc, spectra, frames, maps, stream, steps, warmup):
+    with hb.Plan(desc, 0) as plan:
+        plan.set_forward_model(spectra)
+        with torch.cuda.stream(stream):
+            for _ in range(warmup):
+                plan.estimate(frames, maps, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(steps):
+                plan.estimate(frames, maps, stream)
+        torch.cuda.synchronize()
+        return steps * frames.shape[0] / (time.perf_counter() - t0)
+
+
+def table1_analogue(a, hb, torch, synth, frames, maps, stream, settings):
+    """The paper's speed comparison in kind, on the same frames and grid:
+    posterior on every pixel (levels 0), the proposed method with 1 and 3 Haar
+    levels, and Tikhonov on every coefficient."""
+    H, W = frames.shape[1], frames.shape[2]
+    modes = {"bayes_full_resolution": dict(levels=0), "proposed_w1": dict(levels=1),
+             "proposed_w3": dict(levels=3), "tikhonov": dict(levels=1, lowpass=hb.HB_LOWPASS_TIKHONOV)}
+    out = {}
+    for name, m in modes.items():
+        desc = hb.make_desc(W, H, levels=m["levels"], dtype=a.dtype, max_batch=frames.shape[0], grid_thb=a.grid,
+                            grid_so2=a.grid, lam=settings["lam"], sigma=settings["sigma"],
+                            lowpass=m.get("lowpass", hb.HB_LOWPASS_BAYES))
+        steps = 3 if m["levels"] == 0 else 10
+        out[name] = round(time_plan(hb, torch, desc, synth.spectra(), frames, maps, stream, steps, 1), 2)
+        log(f"table 1 analogue: {name} {out[name]} frames/s", a.quiet)
+    base = out["bayes_full_resolution"]
+    pbase = PAPER_TABLE1_HZ["bayes_full_resolution"]
+    return {"frames_per_s": out, "speedup_vs_full_resolution": {k: round(v / base, 2) for k, v in out.items()},
+            "paper_hz": PAPER_TABLE1_HZ,
+            "paper_speedup_vs_full_resolution": {k: round(v / pbase, 2) for k, v in PAPER_TABLE1_HZ.items()},
+            "grid": f"{a.grid}x{a.grid}", "frames": "the benchmark's 1920x1080 frames"}
 
 
 SERVE_MAX_BATCH = {(480, 640): 8, (1024, 1280): 6, (1080, 1920): 4, (2160, 3840): 2}
@@ -208,6 +250,30 @@ def main():
     stage["log_haar_plus_recompose_GBps"] = hbm_bytes / ((stage["log_haar_ms"] + stage["recompose_ms"]) * 1e-3) / 1e9
 
     plan.close()
+
+    table1 = None if a.no_table1 else table1_analogue(a, hb, torch, synth, frames, maps, stream, settings)
+
+    # The same frames stored in FP16 (device-side RNE cast), same plan settings.
+    half = None
+    if a.dtype == "f32":
+        frames16 = frames.half()
+        desc16 = hb.make_desc(W, H, levels=a.levels, dtype="f16", max_batch=B, grid_thb=a.grid,
+                              grid_so2=a.grid, lam=settings["lam"], sigma=settings["sigma"], grid_split=a.split)
+        with hb.Plan(desc16, 0) as plan16:
+            plan16.set_forward_model(synth.spectra())
+            with torch.cuda.stream(stream):
+                for _ in range(a.warmup):
+                    plan16.estimate(frames16, maps, stream)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                for _ in range(a.steps):
+                    plan16.estimate(frames16, maps, stream)
+            torch.cuda.synchronize()
+            fps16 = a.steps * B / (time.perf_counter() - t1)
+        half = {"frames_per_s": round(fps16, 3), "vs_fp32": round(fps16 / fps, 4)}
+        log(f"fp16 storage: {fps16:.1f} frames/s", a.quiet)
+        del frames16
     del frames, maps
     torch.cuda.empty_cache()
     serve = serving(a) if a.serve_seconds > 0 else None
@@ -229,6 +295,8 @@ def main():
         "mpixel_per_s": round(fps * H * W / 1e6, 2),
         "stages_ms_per_call": {k: round(v, 4) for k, v in stage.items()},
         "roofline": roofline,
+        "fp16_storage": half,
+        "table1_analogue": table1,
         "cpu_baseline": cpu,
         "p99_latency_ms_16_streams": serve["p99_ms"] if serve else None,
         "serving": serve,

@@ -57,3 +57,59 @@ def test_largest_frame_3840x2160(torch_cuda):
     gpu = run(fr[None])
     hbtest.sampled_parity(gpu, fr[None], "f16", s, hbtest.crops(2160, 3840, 2, 32, 8, 5), where="4k")
     run.close()
+
+
+U_ROUND = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+def _posterior_jacobian(c, mu, ybar, sigma, h=1e-6):
+    from oracle import hb_oracle as orc
+    J = np.zeros((2, 3))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        J[:, k] = (orc.posterior_mean(c, mu, ybar + e, sigma) - orc.posterior_mean(c, mu, ybar - e, sigma)) / (2 * h)
+    return J
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_half_storage_error_bound_vs_unquantised(torch_cuda, dtype):
+    """Half-precision storage against the oracle on the unquantised (FP32)
+    frames.  Rounding each intensity changes its log-attenuation by at most
+    u (unit roundoff of the storage type), so per pixel
+        |dc| <= u (||J_post||_inf + 2 ||M||_inf) + 1e-4 uM,
+    with J_post the oracle posterior mean's Jacobian at the pixel's block
+    (central differences) and M the Tikhonov operator."""
+    from oracle import hb_oracle as orc
+    w16 = synth.config4(dtype)
+    f32, _, _ = synth.stereo_pair(2, "f32")
+    s = w16.plan
+    run = hbtest.GpuRun(1280, 1024, s, dtype=dtype, max_batch=2)
+    gpu = run(w16.frames)
+    Mi = np.abs(run.plan.info()["M"]).sum(axis=1).max()
+    run.close()
+    model = hbtest.oracle_model(synth.spectra())
+    cg, mug = orc.grid(hbtest.oracle_params(16, 16, s), model)
+    u = U_ROUND[dtype]
+    worst_ratio, errs = 0.0, {k: [] for k in ("hb", "hbo2", "so2")}
+    for (r, c, hh, ww) in hbtest.crops(1024, 1280, 1, 16, 6, 7):
+        sub = np.ascontiguousarray(f32[:, r:r + hh, c:c + ww])
+        ora = hbtest.run_oracle(sub, "f32", s)
+        g = gpu[:, :, r:r + hh, c:c + ww].astype(np.float64)
+        y = -np.log(np.maximum(sub.astype(np.float64), 1e-4))
+        ybar = y.reshape(2, hh // 2, 2, ww // 2, 2, 3).mean(axis=(2, 4))
+        for v in range(2):
+            for bi in range(hh // 2):
+                for bj in range(ww // 2):
+                    J = _posterior_jacobian(cg, mug, ybar[v, bi, bj], s["sigma"])
+                    bound = u * (np.abs(J).sum(axis=1).max() + 2 * Mi) + 1e-4
+                    blk = (slice(2 * bi, 2 * bi + 2), slice(2 * bj, 2 * bj + 2))
+                    d = np.abs(g[v, :2][(slice(None),) + blk] - ora[v, :2][(slice(None),) + blk]).max()
+                    worst_ratio = max(worst_ratio, d / bound)
+        errs["hb"].append(np.abs(g[:, 0] - ora[:, 0]).ravel())
+        errs["hbo2"].append(np.abs(g[:, 1] - ora[:, 1]).ravel())
+        m = ora[:, 2] >= 1.0
+        errs["so2"].append(np.abs(g[:, 3] - ora[:, 3])[m].ravel())
+    stats = {k: (float(np.concatenate(v).max()), float(np.sqrt(np.mean(np.concatenate(v) ** 2)))) for k, v in errs.items()}
+    print(dtype, "vs unquantised: max/RMS", stats, "worst |dc|/bound", worst_ratio)
+    assert worst_ratio <= 1.0
