@@ -267,8 +267,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
 // upper bound over the super-tiles' boxes.  If m_up - m_lo <= kFarGap for the
 // whole wave, m = m_lo and every weight lies in [0, 2^kFarGap]; otherwise the
 // wave first takes the exact maximum over its nodes.  Moments are accumulated
-// relative to the super-tile's centre inside a super-tile, then merged with
-// Kahan compensation relative to the pixel's anchor (its best probe node).
+// relative to the super-tile's centre inside a super-tile and merged relative
+// to the pixel's anchor (its best probe node); the partial sums of the lanes
+// are combined with compensated pairwise steps and the grid splits with Kahan
+// compensation (recomposition kernel).
 //
 // Two kernels share this: k_posterior (MFMA logits, used when every
 // super-tile is compact in scaled units) and k_posterior_direct (VALU
@@ -283,6 +285,21 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
     const float t = s + y;
     c = (t - s) - y;
     s = t;
+}
+
+// Sum over the 16 lanes of a row (lanes l ^ 8, 4, 2, 1), each pairwise step
+// exact up to a carried error term (two-sum), the error added at the end.
+__device__ __forceinline__ float lane_sum16(float x) {
+    float e = 0.0f;
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) {
+        const float y = __shfl_xor(x, o), ye = __shfl_xor(e, o);
+        float s, err;
+        two_sum(x, y, s, err);
+        x = s;
+        e = (e + ye) + err;
+    }
+    return x + e;
 }
 
 __device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) {
@@ -468,11 +485,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
             anc_hb[b][q] = __shfl(ref.ahb, b * 16 + 4 * lk + q);
             anc_ox[b][q] = __shfl(ref.aox, b * 16 + 4 * lk + q);
         }
-    float R0[PB][4], R1[PB][4], R2[PB][4], K0[PB][4], K1[PB][4], K2[PB][4];
+    float R0[PB][4], R1[PB][4], R2[PB][4];
 #pragma unroll
     for (int b = 0; b < PB; ++b)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) R0[b][q] = R1[b][q] = R2[b][q] = K0[b][q] = K1[b][q] = K2[b][q] = 0.0f;
+        for (int q = 0; q < 4; ++q) R0[b][q] = R1[b][q] = R2[b][q] = 0.0f;
 
     // Exact skipping.  A chunk (or super-tile) whose logit upper bound lies
     // more than kSkipLog2 below every pixel's reference contributes weights
@@ -575,29 +592,23 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
         for (int b = 0; b < PB; ++b)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                kahan_add(R0[b][q], K0[b][q], L0[b][q]);
-                kahan_add(R1[b][q], K1[b][q], fmaf(chb - anc_hb[b][q], L0[b][q], L1[b][q]));
-                kahan_add(R2[b][q], K2[b][q], fmaf(cox - anc_ox[b][q], L0[b][q], L2[b][q]));
+                R0[b][q] += L0[b][q];
+                R1[b][q] += fmaf(chb - anc_hb[b][q], L0[b][q], L1[b][q]);
+                R2[b][q] += fmaf(cox - anc_ox[b][q], L0[b][q], L2[b][q]);
             }
     }
 
     if (a.work && lane == 0) atomicAdd(a.work, (unsigned long long)executed * PW * kChunkNodes);
 
-    // Reduce over the 16 node lanes of each row, then lanes with lp == 0 write.
+    // Reduce over the 16 node lanes of each row with compensated (two-sum)
+    // pairwise steps, then lanes with lp == 0 write.
 #pragma unroll
     for (int b = 0; b < PB; ++b)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            float x0 = R0[b][q], x1 = R1[b][q], x2 = R2[b][q];
-#pragma unroll
-            for (int o = 8; o >= 1; o >>= 1) {
-                x0 += __shfl_xor(x0, o);
-                x1 += __shfl_xor(x1, o);
-                x2 += __shfl_xor(x2, o);
-            }
-            R0[b][q] = x0;
-            R1[b][q] = x1;
-            R2[b][q] = x2;
+            R0[b][q] = lane_sum16(R0[b][q]);
+            R1[b][q] = lane_sum16(R1[b][q]);
+            R2[b][q] = lane_sum16(R2[b][q]);
         }
     float *out = a.part + ((size_t)w.f * a.split + w.split) * kPartFields * a.LL;
 #pragma unroll
