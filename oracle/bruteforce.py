@@ -79,15 +79,21 @@ def grid_nodes(thb_min, thb_max, gt, so2_min, so2_max, gs, mu_fn):
     return c, mu_fn(c)
 
 
-def posterior_mean(c: np.ndarray, mu: np.ndarray, ybar: np.ndarray, sigma: float) -> np.ndarray:
-    ll = -np.sum((ybar[None, :] - mu) ** 2, axis=1) / (2.0 * sigma ** 2)
+def posterior_mean(c: np.ndarray, mu: np.ndarray, ybar: np.ndarray, sigma: float,
+                   illumination: int = 0) -> np.ndarray:
+    r = ybar[None, :] - mu
+    if illumination:
+        # integrating a flat prior over b*(1,1,1) leaves the residual's
+        # component orthogonal to (1,1,1): the projector I - 11'/3
+        r = r @ (np.eye(3) - np.full((3, 3), 1.0 / 3.0))
+    ll = -np.sum(r ** 2, axis=1) / (2.0 * sigma ** 2)
     lw = ll - logsumexp(ll)
     return np.exp(lw) @ c
 
 
 def estimate(frames: np.ndarray, levels: int, spectra, grid: dict, lambda_rel: float,
              sigma: float, floor: float = 1e-4, ref=None, lowpass: int = 0,
-             thb_eps: float = 1e-3) -> np.ndarray:
+             thb_eps: float = 1e-3, illumination: int = 0) -> np.ndarray:
     """frames [H][W][3] -> maps [4][H][W]."""
     eps_hb, eps_hbo2, response, path_cm = spectra
     h, w, _ = frames.shape
@@ -111,7 +117,7 @@ def estimate(frames: np.ndarray, levels: int, spectra, grid: dict, lambda_rel: f
         cg, mug = grid_nodes(grid["thb_min"], grid["thb_max"], grid["grid_thb"],
                              grid["so2_min"], grid["so2_max"], grid["grid_so2"], mu_fn)
         for i in ll_idx:
-            conc[i] = scale * posterior_mean(cg, mug, coef[i] / scale, sigma)
+            conc[i] = scale * posterior_mean(cg, mug, coef[i] / scale, sigma, illumination)
     else:
         mref = mu_fn(np.asarray(ref))
         for i in ll_idx:

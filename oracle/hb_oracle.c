@@ -200,13 +200,25 @@ void orc_haar_inverse(const double *coef, int h, int w, int levels, double *x) {
  * Posterior mean on the low-pass band: uniform prior over the grid nodes,
  * Gaussian likelihood l_g = -|ybar - mu_g|^2 / (2 sigma^2), weights
  * exp(l_g - max l), mean of (Hb, HbO2) under those weights.
+ *
+ * Illumination term (the constant column of the attenuation coefficients,
+ * Method, before Eq. 9: a change that is the same at every wavelength).  In
+ * log space it adds b (1, 1, 1) to the observation; with a flat prior on b
+ * the Gaussian integral over b leaves the likelihood of the residual with its
+ * channel mean removed: l_g = -|d - mean(d)|^2 / (2 sigma^2), d = ybar - mu_g.
  * ------------------------------------------------------------------------- */
 void orc_posterior_mean(const double *c, const double *mu, long G, const double ybar[3],
-                        double sigma, double out[2]) {
+                        double sigma, int illumination, double out[2]) {
     double *l = (double *)malloc(sizeof(double) * (size_t)G);
     double mx = -INFINITY;
     for (long g = 0; g < G; ++g) {
         double d0 = ybar[0] - mu[g * 3 + 0], d1 = ybar[1] - mu[g * 3 + 1], d2 = ybar[2] - mu[g * 3 + 2];
+        if (illumination) {
+            const double dm = (d0 + d1 + d2) / 3.0;
+            d0 -= dm;
+            d1 -= dm;
+            d2 -= dm;
+        }
         l[g] = -(d0 * d0 + d1 * d1 + d2 * d2) / (2.0 * sigma * sigma);
         if (l[g] > mx) mx = l[g];
     }
@@ -282,7 +294,7 @@ int orc_estimate(const orc_params *p, const orc_model *m, const double *frames, 
                              M[i * 3 + 0] * (ybar[0] - mu_ref[0]) + M[i * 3 + 1] * (ybar[1] - mu_ref[1]) +
                              M[i * 3 + 2] * (ybar[2] - mu_ref[2]);
             } else {
-                orc_posterior_mean(gc, gmu, G, ybar, p->sigma, est);
+                orc_posterior_mean(gc, gmu, G, ybar, p->sigma, p->illumination, est);
             }
             cc[px] = scale * est[0];
             cc[HW + px] = scale * est[1];

@@ -41,6 +41,8 @@ typedef struct {
     double thb_eps;                       /* SO2 = NaN where THb <= thb_eps       */
     double ref_hb, ref_hbo2;              /* linearisation point of E (uM)        */
     int lowpass;                          /* 0 = Bayesian, 1 = Tikhonov           */
+    int illumination;                     /* 1: marginalise a per-pixel additive  */
+                                          /* log offset (same in every channel)   */
 } orc_params;
 
 /* mu(c): RGB log-attenuation of concentration c = (Hb, HbO2). */
@@ -55,9 +57,10 @@ void orc_grid(const orc_params *p, const orc_model *m, double *c, double *mu);
 /* n-level 2D Haar of an h x w plane into the Mallat layout (see hb_oracle.c). */
 void orc_haar_forward(const double *x, int h, int w, int levels, double *coef);
 void orc_haar_inverse(const double *coef, int h, int w, int levels, double *x);
-/* Posterior mean of (Hb, HbO2) over G grid nodes for one observation ybar[3]. */
+/* Posterior mean of (Hb, HbO2) over G grid nodes for one observation ybar[3];
+ * with `illumination` the likelihood integrates out an offset b*(1,1,1). */
 void orc_posterior_mean(const double *c, const double *mu, long G, const double ybar[3],
-                        double sigma, double out[2]);
+                        double sigma, int illumination, double out[2]);
 /* Whole path.  frames [n][h][w][3]; maps [n][4][h][w] = Hb, HbO2, THb, SO2.
  * Returns 0, or a negative value for invalid arguments. */
 int orc_estimate(const orc_params *p, const orc_model *m, const double *frames, int n,

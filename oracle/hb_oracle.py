@@ -50,7 +50,7 @@ def lib() -> ctypes.CDLL:
         L.orc_grid.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, dp]
         L.orc_haar_forward.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc_haar_inverse.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
-        L.orc_posterior_mean.argtypes = [dp, dp, ctypes.c_long, dp, ctypes.c_double, dp]
+        L.orc_posterior_mean.argtypes = [dp, dp, ctypes.c_long, dp, ctypes.c_double, ctypes.c_int, dp]
         L.orc_estimate.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_int, dp]
         L.orc_estimate.restype = ctypes.c_int
         L.orc_threads.restype = ctypes.c_int
@@ -74,7 +74,7 @@ class _Params(ctypes.Structure):
                 ("lambda_rel", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("floor", ctypes.c_double), ("thb_eps", ctypes.c_double),
                 ("ref_hb", ctypes.c_double), ("ref_hbo2", ctypes.c_double),
-                ("lowpass", ctypes.c_int)]
+                ("lowpass", ctypes.c_int), ("illumination", ctypes.c_int)]
 
 
 def _dp(a: np.ndarray):
@@ -118,6 +118,7 @@ class Params:
     ref_hb: Optional[float] = None     # default: grid centre
     ref_hbo2: Optional[float] = None
     lowpass: int = 0                   # 0 Bayesian, 1 Tikhonov
+    illumination: int = 0              # 1: integrate out a per-pixel log offset
 
     def ref(self) -> Tuple[float, float]:
         if self.ref_hb is not None and self.ref_hbo2 is not None:
@@ -131,7 +132,7 @@ class Params:
         return _Params(self.width, self.height, self.levels, self.grid_thb, self.grid_so2,
                        self.thb_min, self.thb_max, self.so2_min, self.so2_max,
                        self.lambda_rel, self.sigma, self.floor, self.thb_eps, rh, ro,
-                       self.lowpass)
+                       self.lowpass, self.illumination)
 
 
 def mu(model: Model, hb: float, hbo2: float) -> np.ndarray:
@@ -183,12 +184,12 @@ def haar_inverse(c: np.ndarray, levels: int) -> np.ndarray:
     return out
 
 
-def posterior_mean(c: np.ndarray, mu_: np.ndarray, ybar, sigma: float) -> np.ndarray:
+def posterior_mean(c: np.ndarray, mu_: np.ndarray, ybar, sigma: float, illumination: int = 0) -> np.ndarray:
     c = np.ascontiguousarray(c, dtype=np.float64)
     mu_ = np.ascontiguousarray(mu_, dtype=np.float64)
     y = np.ascontiguousarray(ybar, dtype=np.float64)
     out = np.zeros(2)
-    lib().orc_posterior_mean(_dp(c), _dp(mu_), c.shape[0], _dp(y), sigma, _dp(out))
+    lib().orc_posterior_mean(_dp(c), _dp(mu_), c.shape[0], _dp(y), sigma, int(illumination), _dp(out))
     return out
 
 

@@ -104,3 +104,39 @@ def test_nan_observation_propagates(model):
     c, mu = orc.grid(_params(grid_thb=4, grid_so2=4), model)
     out = orc.posterior_mean(c, mu, [np.nan, 0.1, 0.2], 0.01)
     assert np.all(np.isnan(out))
+
+
+def test_illumination_term_is_a_marginal_over_a_log_offset(model):
+    """Integrating exp(-|ybar - mu_g - b (1,1,1)|^2 / (2 sigma^2)) over b (flat
+    prior; numerical quadrature) gives the weights of the illumination term."""
+    from scipy.integrate import quad
+    p = _params(grid_thb=5, grid_so2=4)
+    c, mu = orc.grid(p, model)
+    rng = np.random.default_rng(21)
+    sigma = 0.02
+    for _ in range(3):
+        y = mu[rng.integers(len(mu))] + rng.normal(0, 0.03, 3) + 0.2
+        lw = []
+        for g in range(len(mu)):
+            d = y - mu[g]
+            b0 = d.mean()   # centre the integral on the maximising offset
+            val, _ = quad(lambda b: np.exp(-np.sum((d - b) ** 2) / (2 * sigma ** 2) +
+                                           np.sum((d - b0) ** 2) / (2 * sigma ** 2)), b0 - 1, b0 + 1,
+                          points=[b0], epsabs=0, epsrel=1e-12, limit=200)
+            lw.append(np.log(val) - np.sum((d - b0) ** 2) / (2 * sigma ** 2))
+        lw = np.array(lw)
+        w = np.exp(lw - lw.max())
+        want = (w[:, None] * c).sum(0) / w.sum()
+        got = orc.posterior_mean(c, mu, y, sigma, illumination=1)
+        assert np.allclose(got, want, rtol=1e-8, atol=1e-8)
+
+
+def test_illumination_term_is_offset_invariant(model):
+    p = _params(grid_thb=20, grid_so2=16)
+    c, mu = orc.grid(p, model)
+    y = mu[77] + np.array([0.003, -0.002, 0.004])
+    a = orc.posterior_mean(c, mu, y, 0.01, illumination=1)
+    for b in (-0.3, 0.05, 0.7):
+        assert np.allclose(orc.posterior_mean(c, mu, y + b, 0.01, illumination=1), a, rtol=1e-12, atol=1e-12)
+    # without the term an offset moves the estimate
+    assert not np.allclose(orc.posterior_mean(c, mu, y + 0.05, 0.01), orc.posterior_mean(c, mu, y, 0.01), atol=1e-3)

@@ -119,3 +119,26 @@ def test_rejects_non_divisible_shape(model):
     p = orc.Params(width=6, height=4, levels=2, **GRID)
     with pytest.raises(ValueError):
         orc.estimate(p, model, np.full((4, 6, 3), 0.5))
+
+
+def test_illumination_term_makes_block_gain_invisible(spectra, model):
+    """With the illumination term a common gain on all intensities of a block
+    (a constant log offset in every channel and pixel) changes nothing."""
+    fr = _frame(8, 8, seed=6, sp=spectra)
+    fr2 = fr.copy()
+    fr2[2:4, 4:6] *= 0.8
+    fr2[0:2, 0:2] *= 1.1
+    p = orc.Params(width=8, height=8, levels=1, illumination=1, **GRID)
+    a = orc.estimate(p, model, fr)[0]
+    b = orc.estimate(p, model, fr2)[0]
+    assert np.allclose(a, b, rtol=0, atol=1e-9, equal_nan=True)
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_illumination_term_matches_dense_brute_force(spectra, model, levels):
+    fr = _frame(8, 8, seed=8 + levels, sp=spectra)
+    p = orc.Params(width=8, height=8, levels=levels, illumination=1, **GRID)
+    got = orc.estimate(p, model, fr)[0]
+    want = bf.estimate(fr, levels, (spectra.eps_hb, spectra.eps_hbo2, spectra.response,
+                                    spectra.path_length_cm), GRID, 1e-3, 0.01, illumination=1)
+    assert np.allclose(got, want, rtol=0, atol=1e-11)
