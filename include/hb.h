@@ -75,6 +75,12 @@ typedef struct {
     int32_t lowpass;            /* hb_lowpass_t                                            */
     int32_t grid_split;         /* posterior grid split across workgroups; 0 = automatic
                                    (sized so that max_batch frames fill the GPU)         */
+    int32_t illumination;       /* 1: the low-pass posterior integrates out an unknown
+                                   per-pixel log offset b*(1,1,1) under a flat prior
+                                   (the constant attenuation term for global illumination,
+                                   Method, before Eq. 9): residuals are projected onto the
+                                   plane orthogonal to (1,1,1).  0 (default) = off.  Only
+                                   affects HB_LOWPASS_BAYES; any other value is rejected. */
 } hb_plan_desc_t;
 
 /* Camera sensitivities and attenuation spectra (the camera matrix C and the

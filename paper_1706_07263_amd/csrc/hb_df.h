@@ -11,8 +11,15 @@ namespace hb {
 
 #define HB_HD __host__ __device__ __forceinline__
 
+// The error-free transformations below are exact only if every addition and
+// product in them is rounded on its own: HIP compiles device code with FMA
+// contraction on, which after inlining could fuse a caller's product into
+// the leading addition of a two-sum and lose the product's rounding error
+// from the compensation term.  Each body therefore turns contraction off.
+
 // s + e == a + b exactly (Knuth).
 HB_HD void two_sum(float a, float b, float &s, float &e) {
+#pragma clang fp contract(off)
     s = a + b;
     const float bb = s - a;
     e = (a - (s - bb)) + (b - bb);
@@ -20,12 +27,14 @@ HB_HD void two_sum(float a, float b, float &s, float &e) {
 
 // Requires |a| >= |b| (Dekker).
 HB_HD void fast_two_sum(float a, float b, float &s, float &e) {
+#pragma clang fp contract(off)
     s = a + b;
     e = b - (s - a);
 }
 
 // (hi, lo) += x
 HB_HD void df_add(float &hi, float &lo, float x) {
+#pragma clang fp contract(off)
     float s, e;
     two_sum(hi, x, s, e);
     e += lo;
@@ -34,6 +43,7 @@ HB_HD void df_add(float &hi, float &lo, float x) {
 
 // (hi, lo) += (xh, xl)
 HB_HD void df_add2(float &hi, float &lo, float xh, float xl) {
+#pragma clang fp contract(off)
     float s, e;
     two_sum(hi, xh, s, e);
     e += lo + xl;
@@ -49,6 +59,7 @@ HB_HD void df_add2(float &hi, float &lo, float xh, float xl) {
 //      (|s| <= 0.1716, truncation below 2e-14);
 //   4. ln q = e ln2 + ln(1 + f) + q_lo / q_hi.
 HB_HD void ln_ratio_df(float R, float I, float &hi, float &lo) {
+#pragma clang fp contract(off)
     const float q = R / I;
     const float r = fmaf(-q, I, R);
     const float qlo_rel = (r / I) / q;

@@ -87,6 +87,7 @@ struct HaarArgs {
     const float *M;          // device, 6 floats (FP32 Tikhonov operator)
     float *z;                // [n][6][LL]: high parts R,G,B then low parts
     float2 *det;             // [n][H][W]
+    int project;             // project z onto the plane orthogonal to (1,1,1)
 };
 
 struct PosteriorArgs {

@@ -226,17 +226,42 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
     }
 
     // 5. Centred low-pass observation z = ybar - mu_ref per block, as a
-    //    double-float: ybar - mu_ref = ln(I_ref / R) + mean(u).
+    //    double-float: ybar - mu_ref = ln(I_ref / R) + mean(u).  With the
+    //    illumination term z loses its mean over the channels (the component
+    //    along (1,1,1) that a common log offset can absorb).
     const float invB = 1.0f / (float)B;
-    for (int q = tid; q < s.nb * 3; q += kBlockThreads) {
-        const int j = q / 3, k = q - 3 * j;
-        const float R = (n > 0) ? s_r[k][j] : s_i[k][j];
-        float zh, zl;
-        ln_ratio_df(a.iref[k], R, zh, zl);
-        df_add(zh, zl, s_u[k][j << n] * invB);
-        const size_t o = (size_t)s.br * d.wl + s.blk0 + j;
-        a.z[((size_t)s.f * 6 + k) * d.LL + o] = zh;
-        a.z[((size_t)s.f * 6 + 3 + k) * d.LL + o] = zl;
+    if (!a.project) {
+        for (int q = tid; q < s.nb * 3; q += kBlockThreads) {
+            const int j = q / 3, k = q - 3 * j;
+            const float R = (n > 0) ? s_r[k][j] : s_i[k][j];
+            float zh, zl;
+            ln_ratio_df(a.iref[k], R, zh, zl);
+            df_add(zh, zl, s_u[k][j << n] * invB);
+            const size_t o = (size_t)s.br * d.wl + s.blk0 + j;
+            a.z[((size_t)s.f * 6 + k) * d.LL + o] = zh;
+            a.z[((size_t)s.f * 6 + 3 + k) * d.LL + o] = zl;
+        }
+    } else {
+        for (int j = tid; j < s.nb; j += kBlockThreads) {
+            float zh[3], zl[3];
+            for (int k = 0; k < 3; ++k) {
+                const float R = (n > 0) ? s_r[k][j] : s_i[k][j];
+                ln_ratio_df(a.iref[k], R, zh[k], zl[k]);
+                df_add(zh[k], zl[k], s_u[k][j << n] * invB);
+            }
+            float sh = zh[0], sl = zl[0];
+            df_add2(sh, sl, zh[1], zl[1]);
+            df_add2(sh, sl, zh[2], zl[2]);
+            // (sh + sl) / 3: the remainder of the leading quotient is exact by FMA
+            const float mh = sh * (1.0f / 3.0f);
+            const float ml = (fmaf(-3.0f, mh, sh) + sl) * (1.0f / 3.0f);
+            const size_t o = (size_t)s.br * d.wl + s.blk0 + j;
+            for (int k = 0; k < 3; ++k) {
+                df_add2(zh[k], zl[k], -mh, -ml);
+                a.z[((size_t)s.f * 6 + k) * d.LL + o] = zh[k];
+                a.z[((size_t)s.f * 6 + 3 + k) * d.LL + o] = zl[k];
+            }
+        }
     }
 
     // 6. Tikhonov on every directional coefficient: (Hb, HbO2) = M * (R, G, B).

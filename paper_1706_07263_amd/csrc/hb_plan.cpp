@@ -87,6 +87,7 @@ hb_status_t check_desc(const hb_plan_desc_t *d) {
         return HB_ERR_INVALID_ARG;
     if (d->lowpass != HB_LOWPASS_BAYES && d->lowpass != HB_LOWPASS_TIKHONOV) return HB_ERR_INVALID_ARG;
     if (d->grid_split < 0 || d->grid_split > 256) return HB_ERR_INVALID_ARG;
+    if (d->illumination != 0 && d->illumination != 1) return HB_ERR_INVALID_ARG;
     return HB_OK;
 }
 
@@ -163,8 +164,11 @@ struct ForwardModel {
 // Build the super-tile table (FP64 arithmetic, FP32 storage): scaled
 // log-attenuation of every grid node centred on mu_ref, stored relative to its
 // super-tile centre in the MFMA operand layout, plus moments, boxes and probes.
+// With the illumination term the node vectors are projected onto the plane
+// orthogonal to (1,1,1), as the observations are.
 double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const double mu_ref[3], double scale,
                     int side, std::vector<float> &table) {
+    const bool project = d.illumination && d.lowpass == HB_LOWPASS_BAYES;
     const int GT = d.grid_thb, GS = d.grid_so2;
     const int nsa = (GT + side - 1) / side, nss = (GS + side - 1) / side;
     const int n_sup = nsa * nss;
@@ -193,8 +197,14 @@ double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const doubl
                     cox[n] = thb * so2;
                     double m[3];
                     fm.mu(chb[n], cox[n], m);
+                    double v[3];
+                    for (int k = 0; k < 3; ++k) v[k] = m[k] - mu_ref[k];
+                    if (project) {
+                        const double mean = (v[0] + v[1] + v[2]) / 3.0;
+                        for (int k = 0; k < 3; ++k) v[k] -= mean;
+                    }
                     for (int k = 0; k < 3; ++k) {
-                        mu[3 * n + k] = scale * (m[k] - mu_ref[k]);
+                        mu[3 * n + k] = scale * v[k];
                         cen[k] += mu[3 * n + k];
                     }
                     mhb += chb[n];
@@ -308,6 +318,7 @@ hb_status_t hb_plan_desc_default(hb_plan_desc_t *d) {
     d->thb_eps = 1e-3;
     d->lowpass = HB_LOWPASS_BAYES;
     d->grid_split = 0;
+    d->illumination = 0;
     return HB_OK;
 }
 
@@ -507,6 +518,7 @@ hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_fram
     ha.M = p->d_mf;
     ha.z = p->d_z;
     ha.det = p->d_det;
+    ha.project = p->desc.illumination && p->desc.lowpass == HB_LOWPASS_BAYES;
 
     if (mark(0) != hipSuccess) return HB_ERR_DEVICE;
     if (launch_log_haar(d_frames, n_frames, ha, s) != hipSuccess) return HB_ERR_DEVICE;

@@ -52,7 +52,8 @@ class hb_plan_desc_t(ctypes.Structure):
                 ("intensity_floor", ctypes.c_double),
                 ("ref_thb", ctypes.c_double), ("ref_so2", ctypes.c_double),
                 ("thb_eps", ctypes.c_double),
-                ("lowpass", ctypes.c_int32), ("grid_split", ctypes.c_int32)]
+                ("lowpass", ctypes.c_int32), ("grid_split", ctypes.c_int32),
+                ("illumination", ctypes.c_int32)]
 
 
 class hb_forward_model_t(ctypes.Structure):
@@ -200,8 +201,8 @@ def make_desc(width: int, height: int, levels: int = 1, dtype: str = "f32", max_
               grid_thb: int = 128, grid_so2: int = 128, thb_min: float = 20.0, thb_max: float = 200.0,
               so2_min: float = 0.3, so2_max: float = 1.0, lam: float = 1e-3, sigma: float = 0.01,
               intensity_floor: float = 1e-4, ref_thb: float = math.nan, ref_so2: float = math.nan,
-              thb_eps: float = 1e-3, lowpass: int = HB_LOWPASS_BAYES, grid_split: int = 0
-              ) -> hb_plan_desc_t:
+              thb_eps: float = 1e-3, lowpass: int = HB_LOWPASS_BAYES, grid_split: int = 0,
+              illumination: int = 0) -> hb_plan_desc_t:
     d = hb_plan_desc_default()
     d.width, d.height, d.levels = width, height, levels
     d.frame_dtype = DTYPES[dtype]
@@ -211,6 +212,7 @@ def make_desc(width: int, height: int, levels: int = 1, dtype: str = "f32", max_
     d.lambda_, d.sigma, d.intensity_floor = lam, sigma, intensity_floor
     d.ref_thb, d.ref_so2, d.thb_eps = ref_thb, ref_so2, thb_eps
     d.lowpass, d.grid_split = lowpass, grid_split
+    d.illumination = illumination
     return d
 
 

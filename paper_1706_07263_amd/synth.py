@@ -248,6 +248,15 @@ def _seed(config: int, stream: int, field_id: int) -> int:
     return 1000 * config + 10 * stream + field_id
 
 
+def illumination_gain(height: int, width: int, seed: int, lo: float = 0.7, hi: float = 1.15
+                      ) -> np.ndarray:
+    """Smooth multiplicative illumination field [H][W][1] in [lo, hi]: the same
+    gain on every colour channel of a pixel (a global-illumination change)."""
+    f = make_blob_field(height, width, seed, n_blobs=4)
+    yy, xx = np.mgrid[0:height, 0:width].astype(np.float64)
+    return (lo + (hi - lo) * f.unit(yy, xx))[..., None]
+
+
 def plan_settings(levels: int, grid: int, lam: float = 1e-3, sigma: float = 0.01) -> Dict[str, object]:
     return dict(levels=levels, grid_thb=grid, grid_so2=grid, thb_min=THB_RANGE[0],
                 thb_max=THB_RANGE[1], so2_min=SO2_RANGE[0], so2_max=SO2_RANGE[1],

@@ -28,7 +28,7 @@ def oracle_params(width: int, height: int, settings: Dict[str, object], lowpass:
                    thb_min=float(settings["thb_min"]), thb_max=float(settings["thb_max"]),
                    so2_min=float(settings["so2_min"]), so2_max=float(settings["so2_max"]),
                    lambda_rel=float(settings["lam"]), sigma=float(settings["sigma"]),
-                   lowpass=lowpass)
+                   lowpass=lowpass, illumination=int(settings.get("illumination", 0)))
     if ref is not None:
         p.ref_hb, p.ref_hbo2 = ref
     return p
@@ -67,7 +67,8 @@ class GpuRun:
                                  thb_min=float(settings["thb_min"]), thb_max=float(settings["thb_max"]),
                                  so2_min=float(settings["so2_min"]), so2_max=float(settings["so2_max"]),
                                  lam=float(settings["lam"]), sigma=float(settings["sigma"]),
-                                 lowpass=lowpass, grid_split=grid_split)
+                                 lowpass=lowpass, grid_split=grid_split,
+                                 illumination=int(settings.get("illumination", 0)))
         self.plan = hb.Plan(self.desc, 0)
         self.plan.set_forward_model(sp or synth.spectra())
         self.dtype = dtype

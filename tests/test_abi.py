@@ -51,7 +51,7 @@ int main(void) {
   printf("hb_maps_t %zu\\n", sizeof(hb_maps_t));
   printf("hb_plan_info_t %zu\\n", sizeof(hb_plan_info_t));
   F(hb_plan_desc_t, thb_min) F(hb_plan_desc_t, lambda) F(hb_plan_desc_t, ref_thb)
-  F(hb_plan_desc_t, lowpass) F(hb_plan_desc_t, grid_split)
+  F(hb_plan_desc_t, lowpass) F(hb_plan_desc_t, grid_split) F(hb_plan_desc_t, illumination)
   F(hb_forward_model_t, eps_hb) F(hb_forward_model_t, path_length_cm)
   F(hb_plan_info_t, gamma) F(hb_plan_info_t, grid_split) F(hb_plan_info_t, posterior_kernel) F(hb_plan_info_t, n_nodes)
   return 0;
@@ -81,6 +81,7 @@ def test_status_strings(hb):
 def test_defaults(hb):
     d = hb.hb_plan_desc_default()
     assert (d.width, d.height, d.levels, d.max_batch) == (64, 64, 1, 1)
+    assert d.illumination == 0
     assert (d.grid_thb, d.grid_so2) == (128, 128)
     assert d.lambda_ == 1e-3 and d.sigma == 0.01 and d.intensity_floor == 1e-4
     assert math.isnan(d.ref_thb) and math.isnan(d.ref_so2)
@@ -106,6 +107,7 @@ BAD = [
     (dict(ref_thb=50.0, ref_so2=1.5), "HB_ERR_INVALID_ARG"),
     (dict(lowpass=2), "HB_ERR_INVALID_ARG"),
     (dict(grid_split=-1), "HB_ERR_INVALID_ARG"),
+    (dict(illumination=2), "HB_ERR_INVALID_ARG"),
 ]
 
 

@@ -249,3 +249,57 @@ def test_exact_skipping_keeps_parity(torch_cuda):
     print("evaluated fraction", evaluated / full)
     hbtest.assert_maps_close(gpu, hbtest.run_oracle(fr[None], "f32", s), "skipping")
     run.close()
+
+
+def _lit_frames(h, w, levels_seed=0):
+    """Config-1-like frames under a smooth illumination gain (same on R, G, B)."""
+    fr, _, _ = synth.single_frame(h, w, config=70 + levels_seed)
+    gain = synth.illumination_gain(h, w, seed=90 + levels_seed)
+    return synth.quantise(fr.astype(np.float64) * gain, "f32")[None]
+
+
+@pytest.mark.parametrize("levels,grid", [(1, 32), (2, 64), (1, 16), (0, 24)])
+def test_illumination_term_parity(torch_cuda, levels, grid):
+    """Low-pass posterior with the per-pixel illumination offset integrated
+    out, on both posterior kernels (grid 16 takes the direct one)."""
+    fr = _lit_frames(64, 96, levels)
+    s = _settings(levels=levels, grid=grid, illumination=1)
+    run = hbtest.GpuRun(96, 64, s)
+    gpu = run(fr)
+    err = hbtest.assert_maps_close(gpu, hbtest.run_oracle(fr, "f32", s), f"illum L{levels} G{grid}")
+    print(f"illumination L{levels} G{grid}", run.plan.info()["posterior_kernel"], err)
+    run.close()
+
+
+def test_illumination_observation_is_projected(torch_cuda):
+    """The centred low-pass observation loses its channel mean: it equals the
+    projection of ybar - mu_ref onto the plane orthogonal to (1,1,1)."""
+    fr = _lit_frames(64, 64)
+    s = _settings(levels=1, grid=32, illumination=1)
+    run = hbtest.GpuRun(64, 64, s)
+    run(fr)
+    info = run.plan.info()
+    y = -np.log(np.maximum(fr[0].astype(np.float64), 1e-4))
+    ybar = y.reshape(32, 2, 32, 2, 3).mean(axis=(1, 3)).reshape(-1, 3)
+    d = ybar - info["mu_ref"]
+    want = d - d.mean(axis=1, keepdims=True)
+    zz = run.debug(run.hb.HB_DEBUG_LOWPASS_OBS).astype(np.float64)
+    z = (zz[0] + zz[1]).T
+    assert np.max(np.abs(z - want)) < 3e-9
+    assert np.max(np.abs(z.sum(axis=1))) < 1e-8
+    run.close()
+
+
+def test_illumination_term_ignores_block_gain(torch_cuda):
+    """A gain constant on each 2^n block changes only the low-pass component
+    along (1,1,1), which the term integrates out: the maps agree with those
+    of the unlit frame to the parity tolerance."""
+    fr, _, _ = synth.single_frame(64, 64, config=75)
+    g = synth.illumination_gain(32, 32, seed=3)
+    lit = synth.quantise(fr.astype(np.float64) * np.kron(g, np.ones((2, 2, 1))), "f32")
+    s = _settings(levels=1, grid=48, illumination=1)
+    run = hbtest.GpuRun(64, 64, s)
+    a = run(fr[None])
+    b = run(lit[None])
+    hbtest.assert_maps_close(b, a, "block gain")
+    run.close()
