@@ -31,11 +31,21 @@ FLOPS_PER_PAIR = 15
 EXPS_PER_PAIR = 1
 # HBM bytes per posterior launch of the default workload (8 frames), from the
 # rocprofv3 FETCH_SIZE/WRITE_SIZE runs summarised in
-# profiles/hot_path_1080p_L2_G256_b8.md, valid for the kernel source whose
-# sha256 starts with KERNEL_SHA (reported as null for any other source or
-# workload).
-PROFILED_KERNEL_SHA = "62a59778f4f6d6fb"
-PROFILED_POSTERIOR_TRAFFIC = 143.1e6
+# profiles/hot_path_1080p_L2_G256_b8.md, valid for the device sources whose
+# combined sha256 (kernel_source_sha) starts with PROFILED_KERNEL_SHA; reported
+# as null for any other source or workload.
+PROFILED_KERNEL_SHA = "40386c47e61b172c"
+PROFILED_POSTERIOR_TRAFFIC = 149.84e6
+KERNEL_SOURCES = ("hb_kernels.hip", "hb_internal.h", "hb_df.h")
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1706_07263_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -232,9 +242,7 @@ def main():
     # skipped; the flops of the roofline are those actually executed).
     eval_per_launch = evaluated / max(launches[1], 1) if evaluated else pairs_per_launch
     achieved = eval_per_launch * FLOPS_PER_PAIR / k2_s / 1e12
-    import hashlib
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1706_07263_amd", "csrc", "hb_kernels.hip"), "rb")
-                         .read()).hexdigest()[:16]
+    sha = kernel_source_sha()
     default_workload = (B, a.levels, a.grid, a.dtype, a.split) == (8, 2, 256, "f32", 0)
     traffic = PROFILED_POSTERIOR_TRAFFIC if (sha == PROFILED_KERNEL_SHA and default_workload) else None
     roofline = {"bound": "alu", "kernel": "k_posterior", "achieved": round(achieved, 3),

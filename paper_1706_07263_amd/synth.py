@@ -330,6 +330,67 @@ def config3(frame_indices: Sequence[int] = (0,), dtype: str = "f32") -> Workload
     return Workload("1920x1080 video", fr, dtype, thb, so2, plan_settings(levels=2, grid=256))
 
 
+# Temporal workload: a registered stereo video of tissue whose blood volume
+# pulses with the heart, as in the paper's in vivo experiment (Experiments,
+# Fig. 2).  THb is modulated in time by a cardiac term plus a slower
+# respiratory term; roaming specular highlights add high-frequency noise; the
+# right view is shifted and its red channel slightly miscalibrated (a constant
+# offset between the views).
+
+@dataclasses.dataclass(frozen=True)
+class PulseSpec:
+    n_frames: int = 300
+    fps: float = 30.0
+    pulse_hz: float = 1.25
+    pulse_depth: float = 0.03       # relative THb modulation
+    resp_hz: float = 0.25
+    resp_depth: float = 0.02
+    n_highlights: int = 3           # specular spots per frame
+    highlight_peak: float = 0.6     # blend towards white at a spot's centre
+    shift_px: float = 8.0           # right view
+    red_gain_right: float = 0.98    # right-view calibration mismatch
+
+
+def pulse_thb_factor(spec: PulseSpec, frame: int, phase: float = 0.4) -> float:
+    t = frame / spec.fps
+    return (1.0 + spec.pulse_depth * math.sin(2 * math.pi * spec.pulse_hz * t + phase)
+            + spec.resp_depth * math.sin(2 * math.pi * spec.resp_hz * t))
+
+
+def pulse_video(height: int, width: int, spec: PulseSpec = PulseSpec(), config: int = 6,
+                dtype: str = "f32", frames: Optional[Sequence[int]] = None
+                ) -> Tuple[np.ndarray, np.ndarray]:
+    """Stereo video [2][T][H][W][3] (storage dtype) and the true THb [2][T][H][W]."""
+    sp = spectra()
+    ft = make_blob_field(height, width, _seed(config, 0, 1))
+    fs = make_blob_field(height, width, _seed(config, 0, 2))
+    idx = list(range(spec.n_frames)) if frames is None else list(frames)
+    yy, xx = np.mgrid[0:height, 0:width].astype(np.float64)
+    out = np.empty((2, len(idx), height, width, 3), dtype=np.uint16 if dtype == "bf16" else
+                   (np.float16 if dtype == "f16" else np.float32))
+    thb_out = np.empty((2, len(idx), height, width))
+    for view in range(2):
+        thb0, so2 = truth(height, width, ft, fs, shift_x=view * spec.shift_px)
+        for i, f in enumerate(idx):
+            thb = thb0 * pulse_thb_factor(spec, f)
+            hb, hbo2 = hb_hbo2(thb, so2)
+            clean = render_intensity(hb, hbo2, sp)
+            rng = np.random.default_rng(_seed(config, view, 5) * 100003 + f)
+            spot = np.zeros((height, width))
+            for _ in range(spec.n_highlights):
+                cy, cx = rng.uniform(0, height), rng.uniform(0, width)
+                sd = rng.uniform(0.01, 0.04) * min(height, width)
+                spot = np.maximum(spot, spec.highlight_peak * rng.uniform(0.5, 1.0) *
+                                  np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * sd * sd)))
+            clean = clean + (1.0 - clean) * spot[..., None]
+            if view == 1:
+                clean[..., 0] *= spec.red_gain_right
+            noisy = clean + rng.normal(0.0, NOISE_SIGMA, clean.shape)
+            out[view, i] = quantise(noisy, dtype)
+            thb_out[view, i] = thb
+    return out, thb_out
+
+
 # Serving workload: 16 streams of mixed resolution at 30 fps with Poisson arrivals.
 SERVE_CLASSES = (  # (count, height, width, levels, grid)
     (4, 480, 640, 2, 256),
