@@ -81,6 +81,14 @@ typedef struct {
                                    Method, before Eq. 9): residuals are projected onto the
                                    plane orthogonal to (1,1,1).  0 (default) = off.  Only
                                    affects HB_LOWPASS_BAYES; any other value is rejected. */
+    double posterior_tolerance; /* uM, >= 0.  The posterior skips 4x4-node grid chunks whose
+                                   weights are all provably below 2^-T of the pixel's
+                                   reference weight, with T chosen so that the skipped
+                                   weights move the posterior mean of Hb and HbO2 by at
+                                   most this much (bound: 2 G 2^-T thb_max, G grid nodes;
+                                   the T in use is reported by hb_plan_get_info).  0 = skip
+                                   only chunks whose float32 weights are exactly zero.
+                                   Default 1e-6 uM, 1% of the FP32 parity tolerance.     */
 } hb_plan_desc_t;
 
 /* Camera sensitivities and attenuation spectra (the camera matrix C and the
@@ -111,6 +119,8 @@ typedef struct {
     int32_t n_tiles;      /* grid super-tiles                                                           */
     int32_t posterior_kernel; /* 0 = MFMA logits, 1 = direct VALU (grids too coarse for the former)     */
     int64_t n_nodes;
+    double skip_log2;     /* T: chunks whose logit bound lies more than T below the reference are skipped */
+    double skip_bound;    /* uM, the stated bound on the posterior-mean change from skipping (0: exact)  */
 } hb_plan_info_t;
 
 /* Fill `desc` with defaults: 64x64, 1 level, FP32, max_batch 1, grid 128x128

@@ -37,6 +37,17 @@ namespace hb {
 // R^2 h <= kMfmaPrecisionBudget, the direct kernel otherwise (both meet the
 // parity tolerance; the bound was set from the measured parity errors).
 constexpr double kMfmaPrecisionBudget = 1000.0;
+
+// Posterior chunk skipping.  exp2 of anything below -kExactSkipLog2 is exactly
+// 0 in float32 (the smallest subnormal is 2^-149; the margin covers rounding
+// of bounds and logits), so skipping at this threshold changes no bit.  A
+// tolerance-derived threshold T skips more: every skipped weight is below
+// 2^-T of the pixel's reference weight, while the kept weights sum to at least
+// about 1 (the reference node itself, within rounding; counted as 1/2), so
+// the posterior mean moves by at most 2 G 2^-T max|c_g - c_hat| <= 2 G 2^-T
+// thb_max for G grid nodes.
+constexpr float kExactSkipLog2 = 160.0f;
+constexpr float kMinSkipLog2 = 16.0f;
 constexpr int kChunkNodes = 16;
 constexpr int kSupHdr = 32;
 constexpr int kMaxProbes = 16;
@@ -101,6 +112,7 @@ struct PosteriorArgs {
     int chunks_per_super;
     int split;
     float scale;             // sqrt(log2(e) / (2 sigma^2))
+    float skip_log2;         // chunks bounded more than this below the reference are skipped
     float *part;             // [n][split][kPartFields][LL]
     unsigned long long *work;  // optional: pairs evaluated (pixel x node), added per wave
 };

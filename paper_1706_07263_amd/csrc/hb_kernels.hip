@@ -398,9 +398,6 @@ __device__ __forceinline__ float box_box_bound(const float *box, const float r[6
     return -fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
 }
 
-// exp2 of anything below -kSkipLog2 is exactly 0 in float32 (the smallest
-// subnormal is 2^-149); the margin covers rounding of bounds and logits.
-constexpr float kSkipLog2 = 160.0f;
 // Widening of the observation box for the rounding of high + low parts.
 constexpr float kBoxSlack = 1.0e-3f;
 
@@ -516,11 +513,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) R0[b][q] = R1[b][q] = R2[b][q] = 0.0f;
 
-    // Exact skipping.  A chunk (or super-tile) whose logit upper bound lies
-    // more than kSkipLog2 below every pixel's reference contributes weights
-    // that are exactly 0 in float32, so leaving it out changes no bit.  The
-    // bound is taken between the chunk's box and the box of the wave's
-    // observations (min reference over the wave), one chunk per lane.
+    // Skipping.  A chunk (or super-tile) whose logit upper bound lies more
+    // than skip_log2 below every pixel's reference has every weight below
+    // 2^-skip_log2 (exactly 0 in float32 at kExactSkipLog2, so then leaving
+    // it out changes no bit).  The bound is taken between the chunk's box and
+    // the box of the wave's observations (min reference over the wave), one
+    // chunk per lane.
+    const float nskip = -a.skip_log2;
     float zlo[3], zhi[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) zlo[k] = zhi[k] = ph[k] + pl[k];
@@ -545,7 +544,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
             rbox[k] = (zlo[k] - c) - kBoxSlack;
             rbox[3 + k] = (zhi[k] - c) + kBoxSlack;
         }
-        if (!(box_box_bound(T + 8, rbox) - mmin > -kSkipLog2)) continue;
+        if (!(box_box_bound(T + 8, rbox) - mmin > nskip)) continue;
         const int kk = lk < 3 ? lk : 0;
         const float ch = T[kk], cl = T[3 + kk];
         float av[PB];
@@ -566,7 +565,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
         for (int cg = 0; cg < a.chunks_per_super; cg += 64) {
             const int ct = min(cg + lane, a.chunks_per_super - 1);
             const bool keep = cg + lane < a.chunks_per_super &&
-                              box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > -kSkipLog2;
+                              box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > nskip;
             unsigned long long mask = __ballot(keep);
             if (mask == 0) continue;
             // Walk the kept chunks with two operand buffers: the next chunk's

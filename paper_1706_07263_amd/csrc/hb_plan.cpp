@@ -50,6 +50,7 @@ struct hb_plan_s {
     hb_plan_info_t info{};
     float iref[3] = {1, 1, 1};
     float scale = 1.0f;
+    float skip_log2 = kExactSkipLog2;
 
     bool timing = false;
     std::vector<hipEvent_t> events;  // 4 per recorded call
@@ -88,6 +89,7 @@ hb_status_t check_desc(const hb_plan_desc_t *d) {
     if (d->lowpass != HB_LOWPASS_BAYES && d->lowpass != HB_LOWPASS_TIKHONOV) return HB_ERR_INVALID_ARG;
     if (d->grid_split < 0 || d->grid_split > 256) return HB_ERR_INVALID_ARG;
     if (d->illumination != 0 && d->illumination != 1) return HB_ERR_INVALID_ARG;
+    if (!is_finite(d->posterior_tolerance) || d->posterior_tolerance < 0) return HB_ERR_INVALID_ARG;
     return HB_OK;
 }
 
@@ -319,6 +321,7 @@ hb_status_t hb_plan_desc_default(hb_plan_desc_t *d) {
     d->lowpass = HB_LOWPASS_BAYES;
     d->grid_split = 0;
     d->illumination = 0;
+    d->posterior_tolerance = 1e-6;
     return HB_OK;
 }
 
@@ -380,6 +383,11 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     p->info.grid_split = p->split;
     p->info.n_tiles = p->n_tiles;
     p->info.n_nodes = p->n_nodes;
+    if (desc->posterior_tolerance > 0) {
+        const double t = std::ceil(std::log2(2.0 * (double)p->n_nodes * desc->thb_max / desc->posterior_tolerance));
+        p->skip_log2 = (float)std::min<double>(kExactSkipLog2, std::max<double>(kMinSkipLog2, t));
+    }
+    p->info.skip_log2 = p->skip_log2;
     *out = p;
     return HB_OK;
 }
@@ -470,6 +478,10 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
     const double h_so2 = d.grid_so2 > 1 ? d.thb_max * (d.so2_max - d.so2_min) / (d.grid_so2 - 1) : 0.0;
     p->use_mfma = p->radius * p->radius * std::max(h_thb, h_so2) <= kMfmaPrecisionBudget;
     p->info.posterior_kernel = p->use_mfma ? 0 : 1;
+    // Only the MFMA kernel skips chunks; exact skipping has no error.
+    p->info.skip_bound = (p->use_mfma && p->skip_log2 < kExactSkipLog2)
+                             ? 2.0 * (double)p->n_nodes * std::exp2(-(double)p->skip_log2) * d.thb_max
+                             : 0.0;
     if (hipMemcpy(p->d_tiles, tiles.data(), sizeof(float) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
         return HB_ERR_DEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return HB_ERR_DEVICE;
@@ -536,6 +548,7 @@ hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_fram
         pa.chunks_per_super = (p->side / 4) * (p->side / 4);
         pa.split = p->split;
         pa.scale = p->scale;
+        pa.skip_log2 = p->skip_log2;
         pa.part = p->d_part;
         pa.work = ev ? p->d_work : nullptr;
         if (ev) p->full_pairs += (long long)n_frames * p->dims.LL * p->n_nodes;

@@ -53,7 +53,7 @@ class hb_plan_desc_t(ctypes.Structure):
                 ("ref_thb", ctypes.c_double), ("ref_so2", ctypes.c_double),
                 ("thb_eps", ctypes.c_double),
                 ("lowpass", ctypes.c_int32), ("grid_split", ctypes.c_int32),
-                ("illumination", ctypes.c_int32)]
+                ("illumination", ctypes.c_int32), ("posterior_tolerance", ctypes.c_double)]
 
 
 class hb_forward_model_t(ctypes.Structure):
@@ -75,7 +75,7 @@ class hb_plan_info_t(ctypes.Structure):
                 ("ref_hb", ctypes.c_double), ("ref_hbo2", ctypes.c_double),
                 ("mu_ref", ctypes.c_double * 3), ("grid_split", ctypes.c_int32),
                 ("n_tiles", ctypes.c_int32), ("posterior_kernel", ctypes.c_int32),
-                ("n_nodes", ctypes.c_int64)]
+                ("n_nodes", ctypes.c_int64), ("skip_log2", ctypes.c_double), ("skip_bound", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -168,7 +168,8 @@ def hb_plan_get_info(plan: int) -> Dict[str, object]:
     return dict(E=np.array(info.E[:]).reshape(3, 2), M=np.array(info.M[:]).reshape(2, 3),
                 gamma=info.gamma, ref=(info.ref_hb, info.ref_hbo2), mu_ref=np.array(info.mu_ref[:]),
                 grid_split=info.grid_split, n_tiles=info.n_tiles, n_nodes=info.n_nodes,
-                posterior_kernel=("mfma", "direct")[info.posterior_kernel])
+                posterior_kernel=("mfma", "direct")[info.posterior_kernel],
+                skip_log2=info.skip_log2, skip_bound=info.skip_bound)
 
 
 def hb_plan_set_timing(plan: int, enable: bool) -> None:
@@ -202,7 +203,7 @@ def make_desc(width: int, height: int, levels: int = 1, dtype: str = "f32", max_
               so2_min: float = 0.3, so2_max: float = 1.0, lam: float = 1e-3, sigma: float = 0.01,
               intensity_floor: float = 1e-4, ref_thb: float = math.nan, ref_so2: float = math.nan,
               thb_eps: float = 1e-3, lowpass: int = HB_LOWPASS_BAYES, grid_split: int = 0,
-              illumination: int = 0) -> hb_plan_desc_t:
+              illumination: int = 0, posterior_tolerance: Optional[float] = None) -> hb_plan_desc_t:
     d = hb_plan_desc_default()
     d.width, d.height, d.levels = width, height, levels
     d.frame_dtype = DTYPES[dtype]
@@ -213,6 +214,8 @@ def make_desc(width: int, height: int, levels: int = 1, dtype: str = "f32", max_
     d.ref_thb, d.ref_so2, d.thb_eps = ref_thb, ref_so2, thb_eps
     d.lowpass, d.grid_split = lowpass, grid_split
     d.illumination = illumination
+    if posterior_tolerance is not None:
+        d.posterior_tolerance = posterior_tolerance
     return d
 
 

@@ -68,7 +68,8 @@ class GpuRun:
                                  so2_min=float(settings["so2_min"]), so2_max=float(settings["so2_max"]),
                                  lam=float(settings["lam"]), sigma=float(settings["sigma"]),
                                  lowpass=lowpass, grid_split=grid_split,
-                                 illumination=int(settings.get("illumination", 0)))
+                                 illumination=int(settings.get("illumination", 0)),
+                                 posterior_tolerance=settings.get("posterior_tolerance"))
         self.plan = hb.Plan(self.desc, 0)
         self.plan.set_forward_model(sp or synth.spectra())
         self.dtype = dtype

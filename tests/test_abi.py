@@ -51,9 +51,9 @@ int main(void) {
   printf("hb_maps_t %zu\\n", sizeof(hb_maps_t));
   printf("hb_plan_info_t %zu\\n", sizeof(hb_plan_info_t));
   F(hb_plan_desc_t, thb_min) F(hb_plan_desc_t, lambda) F(hb_plan_desc_t, ref_thb)
-  F(hb_plan_desc_t, lowpass) F(hb_plan_desc_t, grid_split) F(hb_plan_desc_t, illumination)
+  F(hb_plan_desc_t, lowpass) F(hb_plan_desc_t, grid_split) F(hb_plan_desc_t, illumination) F(hb_plan_desc_t, posterior_tolerance)
   F(hb_forward_model_t, eps_hb) F(hb_forward_model_t, path_length_cm)
-  F(hb_plan_info_t, gamma) F(hb_plan_info_t, grid_split) F(hb_plan_info_t, posterior_kernel) F(hb_plan_info_t, n_nodes)
+  F(hb_plan_info_t, gamma) F(hb_plan_info_t, grid_split) F(hb_plan_info_t, posterior_kernel) F(hb_plan_info_t, n_nodes) F(hb_plan_info_t, skip_log2) F(hb_plan_info_t, skip_bound)
   return 0;
 }
 """)
@@ -81,7 +81,7 @@ def test_status_strings(hb):
 def test_defaults(hb):
     d = hb.hb_plan_desc_default()
     assert (d.width, d.height, d.levels, d.max_batch) == (64, 64, 1, 1)
-    assert d.illumination == 0
+    assert d.illumination == 0 and d.posterior_tolerance == 1e-6
     assert (d.grid_thb, d.grid_so2) == (128, 128)
     assert d.lambda_ == 1e-3 and d.sigma == 0.01 and d.intensity_floor == 1e-4
     assert math.isnan(d.ref_thb) and math.isnan(d.ref_so2)
@@ -108,6 +108,8 @@ BAD = [
     (dict(lowpass=2), "HB_ERR_INVALID_ARG"),
     (dict(grid_split=-1), "HB_ERR_INVALID_ARG"),
     (dict(illumination=2), "HB_ERR_INVALID_ARG"),
+    (dict(posterior_tolerance=-1.0), "HB_ERR_INVALID_ARG"),
+    (dict(posterior_tolerance=float("nan")), "HB_ERR_INVALID_ARG"),
 ]
 
 
