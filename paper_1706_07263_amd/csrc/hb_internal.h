@@ -113,6 +113,7 @@ struct PosteriorArgs {
     int split;
     float scale;             // sqrt(log2(e) / (2 sigma^2))
     float skip_log2;         // chunks bounded more than this below the reference are skipped
+    float *gref;             // [n][LL] best probe logit over the whole grid, or null (one split)
     float *part;             // [n][split][kPartFields][LL]
     unsigned long long *work;  // optional: pairs evaluated (pixel x node), added per wave
 };
@@ -133,6 +134,7 @@ struct RecomposeArgs {
 // Launchers (hb_kernels.hip).  They only enqueue work.
 hipError_t launch_tikhonov_fp64(const double *d_in, double *d_out, float *d_mf, hipStream_t s);
 hipError_t launch_log_haar(const void *frames, int n_frames, const HaarArgs &a, hipStream_t s);
+hipError_t launch_reference(const PosteriorArgs &a, hipStream_t s);
 hipError_t launch_posterior(const PosteriorArgs &a, bool mfma, hipStream_t s);
 hipError_t launch_recompose(int n_frames, const RecomposeArgs &a, hipStream_t s);
 

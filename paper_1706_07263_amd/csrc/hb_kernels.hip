@@ -405,28 +405,57 @@ struct PixelRef {
     float m, ahb, aox;
 };
 
+// Best probe of super-tile T for observation r (recentred on T): updates the
+// running best logit and its anchor node.
+__device__ __forceinline__ void probe_supertile(const float *__restrict__ T, const float r[3], float &mlo,
+                                                float &ahb, float &aox) {
+    const int np = __float_as_int(T[14]);
+    for (int i = 0; i < np; ++i) {
+        const float *P = T + kSupHdr + i * kProbeFloats;
+        const float d0 = r[0] - P[0], d1 = r[1] - P[1], d2 = r[2] - P[2];
+        const float tp = -fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+        if (tp > mlo) {
+            mlo = tp;
+            ahb = P[3];
+            aox = P[4];
+        }
+    }
+}
+
 // Per-pixel reference logit and anchor.  Each pixel is handled by LPP lanes
 // (lane / PW selects the part), which split the super-tiles between them.
+// The best probe over the split equals that of a full scan: each lane first
+// probes the super-tile with its highest box bound, then the wave probes only
+// super-tiles whose bound exceeds some lane's best probe so far (a super-tile
+// whose bound is below it cannot hold a better probe).
 template <int PW, int LPP>
 __device__ PixelRef pixel_reference(const PosteriorArgs &a, const WaveWork &w, const float ph[3],
                                     const float pl[3], int part) {
     float mlo = -INFINITY, mup = -INFINITY, ahb = 0.0f, aox = 0.0f;
+    int best = -1;
     for (int si = w.s0 + part; si < w.s1; si += LPP) {
         const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
         float r[3];
         recentre(T, ph, pl, r);
-        mup = fmaxf(mup, box_bound(T + 8, r));
-        const int np = __float_as_int(T[14]);
-        for (int i = 0; i < np; ++i) {
-            const float *P = T + kSupHdr + i * kProbeFloats;
-            const float d0 = r[0] - P[0], d1 = r[1] - P[1], d2 = r[2] - P[2];
-            const float tp = -fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-            if (tp > mlo) {
-                mlo = tp;
-                ahb = P[3];
-                aox = P[4];
-            }
+        const float ub = box_bound(T + 8, r);
+        if (ub > mup || best < 0) {
+            mup = fmaxf(mup, ub);
+            best = si;
         }
+    }
+    if (best >= 0) {
+        const float *__restrict__ T = a.supers + (size_t)best * a.super_stride;
+        float r[3];
+        recentre(T, ph, pl, r);
+        probe_supertile(T, r, mlo, ahb, aox);
+    }
+    for (int si = w.s0 + part; si < w.s1; si += LPP) {
+        const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+        float r[3];
+        recentre(T, ph, pl, r);
+        const bool may = si != best && box_bound(T + 8, r) > mlo;
+        if (!__any(may)) continue;
+        if (si != best) probe_supertile(T, r, mlo, ahb, aox);
     }
     if (LPP == 2) {  // combine the two halves (lower half wins ties)
         const float om = __shfl_xor(mlo, PW), oh = __shfl_xor(ahb, PW), oo = __shfl_xor(aox, PW);
@@ -458,6 +487,45 @@ __device__ PixelRef pixel_reference(const PosteriorArgs &a, const WaveWork &w, c
         ref.m = mx;
     }
     return ref;
+}
+
+// Global reference for split grids: one lane per LL pixel, the best probe
+// logit over all super-tiles (the same search as above without the split).
+// Each split then skips against max(own reference, global reference), so a
+// split far from the pixel's posterior skips against the posterior's peak.
+__global__ __launch_bounds__(kBlockThreads) void k_reference(PosteriorArgs a) {
+    const long long i = (long long)blockIdx.x * kBlockThreads + threadIdx.x;
+    if (i >= (long long)a.n_frames * a.LL) return;
+    const long long f = i / a.LL, p = i - f * a.LL;
+    const float *zf = a.z + (size_t)f * 6 * a.LL;
+    float ph[3], pl[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) load_obs(zf, a.LL, p, k, a.scale, ph[k], pl[k]);
+    float mlo = -INFINITY, mup = -INFINITY, ahb = 0.0f, aox = 0.0f;
+    int best = 0;
+    for (int si = 0; si < a.n_supers; ++si) {
+        const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+        float r[3];
+        recentre(T, ph, pl, r);
+        const float ub = box_bound(T + 8, r);
+        if (ub > mup) {
+            mup = ub;
+            best = si;
+        }
+    }
+    {
+        const float *__restrict__ T = a.supers + (size_t)best * a.super_stride;
+        float r[3];
+        recentre(T, ph, pl, r);
+        probe_supertile(T, r, mlo, ahb, aox);
+    }
+    for (int si = 0; si < a.n_supers; ++si) {
+        const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+        float r[3];
+        recentre(T, ph, pl, r);
+        if (si != best && box_bound(T + 8, r) > mlo) probe_supertile(T, r, mlo, ahb, aox);
+    }
+    a.gref[i] = mlo;
 }
 
 // MFMA kernel: a wave takes PB blocks of 16 LL pixels.  Per super-tile and
@@ -524,6 +592,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) zlo[k] = zhi[k] = ph[k] + pl[k];
     float mmin = ref.m;
+    if (a.gref) {
+        long long p;
+        wave_pixel(a, w, lane % PW, p);
+        mmin = fmaxf(mmin, a.gref[(size_t)w.f * a.LL + p]);
+    }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
 #pragma unroll
@@ -813,6 +886,14 @@ hipError_t launch_log_haar(const void *frames, int n_frames, const HaarArgs &a, 
                                (const uint16_t *)frames, a);
             break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_reference(const PosteriorArgs &a, hipStream_t s) {
+    const long long n = (long long)a.n_frames * a.LL;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reference, dim3((unsigned)((n + kBlockThreads - 1) / kBlockThreads)), dim3(kBlockThreads),
+                       0, s, a);
     return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ struct hb_plan_s {
     float *d_z = nullptr;
     float2 *d_det = nullptr;
     float *d_part = nullptr;
+    float *d_gref = nullptr;  // global posterior reference per LL pixel (split grids)
     float2 *d_est = nullptr;
     unsigned long long *d_work = nullptr;  // posterior pairs evaluated while timing
     size_t bytes = 0;
@@ -133,6 +134,7 @@ void free_plan(hb_plan_s *p) {
     (void)hipFree(p->d_z);
     (void)hipFree(p->d_det);
     (void)hipFree(p->d_part);
+    (void)hipFree(p->d_gref);
     (void)hipFree(p->d_est);
     (void)hipFree(p->d_work);
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
@@ -373,6 +375,8 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_det, sizeof(float2) * nb * HW);
     if (st == HB_OK && desc->lowpass == HB_LOWPASS_BAYES)
         st = dev_alloc(p, (void **)&p->d_part, sizeof(float) * nb * p->split * kPartFields * LL);
+    if (st == HB_OK && desc->lowpass == HB_LOWPASS_BAYES && p->split > 1)
+        st = dev_alloc(p, (void **)&p->d_gref, sizeof(float) * nb * LL);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_est, sizeof(float2) * nb * LL);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_work, sizeof(unsigned long long));
     if (st == HB_OK && hipMemset(p->d_work, 0, sizeof(unsigned long long)) != hipSuccess) st = HB_ERR_DEVICE;
@@ -552,6 +556,10 @@ hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_fram
         pa.part = p->d_part;
         pa.work = ev ? p->d_work : nullptr;
         if (ev) p->full_pairs += (long long)n_frames * p->dims.LL * p->n_nodes;
+        if (p->use_mfma && p->d_gref) {
+            pa.gref = p->d_gref;
+            if (launch_reference(pa, s) != hipSuccess) return HB_ERR_DEVICE;
+        }
         if (launch_posterior(pa, p->use_mfma, s) != hipSuccess) return HB_ERR_DEVICE;
     }
     if (mark(2) != hipSuccess) return HB_ERR_DEVICE;
