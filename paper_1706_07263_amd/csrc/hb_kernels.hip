@@ -422,52 +422,122 @@ __device__ __forceinline__ void probe_supertile(const float *__restrict__ T, con
     }
 }
 
-// Per-pixel reference logit and anchor.  Each pixel is handled by LPP lanes
-// (lane / PW selects the part), which split the super-tiles between them.
-// The best probe over the split equals that of a full scan: each lane first
-// probes the super-tile with its highest box bound, then the wave probes only
-// super-tiles whose bound exceeds some lane's best probe so far (a super-tile
-// whose bound is below it cannot hold a better probe).
-template <int PW, int LPP>
-__device__ PixelRef pixel_reference(const PosteriorArgs &a, const WaveWork &w, const float ph[3],
-                                    const float pl[3], int part) {
-    float mlo = -INFINITY, mup = -INFINITY, ahb = 0.0f, aox = 0.0f;
-    int best = -1;
-    for (int si = w.s0 + part; si < w.s1; si += LPP) {
-        const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
-        float r[3];
-        recentre(T, ph, pl, r);
-        const float ub = box_bound(T + 8, r);
-        if (ub > mup || best < 0) {
-            mup = fmaxf(mup, ub);
-            best = si;
+// Observation box of the wave (every lane's pixel), for bounds that hold for
+// all of its pixels at once.
+__device__ __forceinline__ void wave_obs_box(const float ph[3], const float pl[3], float zlo[3], float zhi[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) zlo[k] = zhi[k] = ph[k] + pl[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            zlo[k] = fminf(zlo[k], __shfl_xor(zlo[k], o));
+            zhi[k] = fmaxf(zhi[k], __shfl_xor(zhi[k], o));
+        }
+}
+
+// Upper bound of the logit between the wave's observation box and the node
+// box of super-tile si (widened for the rounding of high + low parts).
+__device__ __forceinline__ float wave_super_bound(const PosteriorArgs &a, int si, const float zlo[3],
+                                                  const float zhi[3], float rbox[6]) {
+    const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float c = T[k] + T[3 + k];
+        rbox[k] = (zlo[k] - c) - kBoxSlack;
+        rbox[3 + k] = (zhi[k] - c) + kBoxSlack;
+    }
+    return box_box_bound(T + 8, rbox);
+}
+
+// Probes i = part, part + LPP, ... of super-tile T for observation r.
+template <int LPP>
+__device__ __forceinline__ void probe_part(const float *__restrict__ T, const float r[3], int part, float &mlo,
+                                           float &ahb, float &aox) {
+    const int np = __float_as_int(T[14]);
+    for (int i = part; i < np; i += LPP) {
+        const float *P = T + kSupHdr + i * kProbeFloats;
+        const float d0 = r[0] - P[0], d1 = r[1] - P[1], d2 = r[2] - P[2];
+        const float tp = -fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+        if (tp > mlo) {
+            mlo = tp;
+            ahb = P[3];
+            aox = P[4];
         }
     }
-    if (best >= 0) {
+}
+
+// Per-pixel reference logit and anchor: the best probe over the split's
+// super-tiles.  Each pixel is handled by LPP lanes (lane / PW selects the
+// part), which split every super-tile's probes between them.  The wave first
+// bounds all super-tiles at once (one per lane, against its observation box),
+// probes the one with the highest bound, then only super-tiles whose bound
+// exceeds the lowest best probe of the wave: the result equals a full probe
+// scan (a super-tile bounded below a pixel's best probe cannot improve it).
+template <int PW, int LPP>
+__device__ PixelRef pixel_reference(const PosteriorArgs &a, const WaveWork &w, const float ph[3],
+                                    const float pl[3], int part, const float zlo[3], const float zhi[3]) {
+    const int lane = threadIdx.x & 63;
+    float mup = -INFINITY;
+    int best = w.s0;
+    for (int g = w.s0; g < w.s1; g += 64) {
+        const int si = g + lane;
+        float rbox[6];
+        float bm = si < w.s1 ? wave_super_bound(a, si, zlo, zhi, rbox) : -INFINITY;
+        int bi = si;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {  // wave arg-max, lowest index on ties
+            const float ob = __shfl_xor(bm, o);
+            const int oi = __shfl_xor(bi, o);
+            if (ob > bm || (ob == bm && oi < bi)) {
+                bm = ob;
+                bi = oi;
+            }
+        }
+        if (bm > mup) {
+            mup = bm;
+            best = bi;
+        }
+    }
+    best = __builtin_amdgcn_readfirstlane(best);
+    float mlo = -INFINITY, ahb = 0.0f, aox = 0.0f;
+    auto combine = [&]() {  // the LPP lanes of a pixel agree (lower half wins ties)
+        if (LPP == 2) {
+            const float om = __shfl_xor(mlo, PW), oh = __shfl_xor(ahb, PW), oo = __shfl_xor(aox, PW);
+            const bool take = part == 0 ? (om > mlo) : !(mlo > om);
+            if (take) {
+                mlo = om;
+                ahb = oh;
+                aox = oo;
+            }
+        }
+    };
+    {
         const float *__restrict__ T = a.supers + (size_t)best * a.super_stride;
         float r[3];
         recentre(T, ph, pl, r);
-        probe_supertile(T, r, mlo, ahb, aox);
+        probe_part<LPP>(T, r, part, mlo, ahb, aox);
+        combine();
     }
-    for (int si = w.s0 + part; si < w.s1; si += LPP) {
-        const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
-        float r[3];
-        recentre(T, ph, pl, r);
-        const bool may = si != best && box_bound(T + 8, r) > mlo;
-        if (!__any(may)) continue;
-        if (si != best) probe_supertile(T, r, mlo, ahb, aox);
-    }
-    if (LPP == 2) {  // combine the two halves (lower half wins ties)
-        const float om = __shfl_xor(mlo, PW), oh = __shfl_xor(ahb, PW), oo = __shfl_xor(aox, PW);
-        const float ou = __shfl_xor(mup, PW);
-        const bool take = part == 0 ? (om > mlo) : !(mlo > om);
-        if (take) {
-            mlo = om;
-            ahb = oh;
-            aox = oo;
+    float mwave = mlo;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mwave = fminf(mwave, __shfl_xor(mwave, o));
+    for (int g = w.s0; g < w.s1; g += 64) {
+        const int sl = g + lane;
+        float rbox[6];
+        const bool cand = sl < w.s1 && sl != best && !(wave_super_bound(a, sl, zlo, zhi, rbox) <= mwave);
+        unsigned long long mask = __ballot(cand);
+        while (mask) {
+            const int si = g + __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+            float r[3];
+            recentre(T, ph, pl, r);
+            if (!__any(box_bound(T + 8, r) > mlo)) continue;
+            probe_part<LPP>(T, r, part, mlo, ahb, aox);
         }
-        mup = fmaxf(mup, ou);
     }
+    combine();
     PixelRef ref{mlo, ahb, aox};
     if (__any(!(mup - mlo <= kFarGap))) {
         // Exact maximum over this split's nodes, difference form.
@@ -554,7 +624,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) load_obs(zf, a.LL, p, k, sc, ph[k], pl[k]);
     }
-    const PixelRef ref = pixel_reference<PW, LPP>(a, w, ph, pl, part);
+    float zlo[3], zhi[3];
+    wave_obs_box(ph, pl, zlo, zhi);
+    const PixelRef ref = pixel_reference<PW, LPP>(a, w, ph, pl, part, zlo, zhi);
 
     // A operand of block b: lane (lp, lk) holds coordinate lk of pixel b*16 + lp
     // (lk == 3: the homogeneous 1, and m for the constant term).
@@ -588,9 +660,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
     // the box of the wave's observations (min reference over the wave), one
     // chunk per lane.
     const float nskip = -a.skip_log2;
-    float zlo[3], zhi[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) zlo[k] = zhi[k] = ph[k] + pl[k];
     float mmin = ref.m;
     if (a.gref) {
         long long p;
@@ -598,26 +667,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
         mmin = fmaxf(mmin, a.gref[(size_t)w.f * a.LL + p]);
     }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            zlo[k] = fminf(zlo[k], __shfl_xor(zlo[k], o));
-            zhi[k] = fmaxf(zhi[k], __shfl_xor(zhi[k], o));
-        }
-        mmin = fminf(mmin, __shfl_xor(mmin, o));
-    }
+    for (int o = 32; o >= 1; o >>= 1) mmin = fminf(mmin, __shfl_xor(mmin, o));
     const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
     unsigned executed = 0;   // chunks evaluated by this wave
-    for (int si = w.s0; si < w.s1; ++si) {
+    // Super-tiles are tested one per lane; the kept ones are walked in order.
+    for (int g = w.s0; g < w.s1; g += 64) {
+      float rbox[6];
+      const int sl = g + lane;
+      unsigned long long smask = __ballot(sl < w.s1 && wave_super_bound(a, sl, zlo, zhi, rbox) - mmin > nskip);
+      while (smask) {
+        const int si = g + __builtin_ctzll(smask);
+        smask &= smask - 1;
         const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
-        float rbox[6];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float c = T[k] + T[3 + k];
-            rbox[k] = (zlo[k] - c) - kBoxSlack;
-            rbox[3 + k] = (zhi[k] - c) + kBoxSlack;
-        }
-        if (!(box_box_bound(T + 8, rbox) - mmin > nskip)) continue;
+        wave_super_bound(a, si, zlo, zhi, rbox);
         const int kk = lk < 3 ? lk : 0;
         const float ch = T[kk], cl = T[3 + kk];
         float av[PB];
@@ -693,6 +755,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
                 R1[b][q] += fmaf(chb - anc_hb[b][q], L0[b][q], L1[b][q]);
                 R2[b][q] += fmaf(cox - anc_ox[b][q], L0[b][q], L2[b][q]);
             }
+      }
     }
 
     if (a.work && lane == 0) atomicAdd(a.work, (unsigned long long)executed * PW * kChunkNodes);
@@ -739,7 +802,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
     float ph[3], pl[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) load_obs(zf, a.LL, p, k, a.scale, ph[k], pl[k]);
-    const PixelRef ref = pixel_reference<PW, 1>(a, w, ph, pl, 0);
+    float zlo[3], zhi[3];
+    wave_obs_box(ph, pl, zlo, zhi);
+    const PixelRef ref = pixel_reference<PW, 1>(a, w, ph, pl, 0, zlo, zhi);
     const float nm = -ref.m;
     float R0 = 0.f, R1 = 0.f, R2 = 0.f, K0 = 0.f, K1 = 0.f, K2 = 0.f;
     for (int si = w.s0; si < w.s1; ++si) {
