@@ -92,6 +92,8 @@ struct Dims {
 
 struct HaarArgs {
     Dims d;
+    int n_frames;
+    int vec4;                // frames pointer aligned to 4 stored values (vector loads allowed)
     int dtype;
     float floor;
     float iref[3];           // float32 reference intensities exp(-mu_ref)

@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "hb_df.h"
 #include "hb_internal.h"
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
         s_i[k][r * Wt + c] = v;
         s_u[k][r * Wt + c] = v;
     };
-    if ((d.W & 3) == 0 && (run & 3) == 0) {
+    if (a.vec4 && (d.W & 3) == 0 && (run & 3) == 0) {
         const int r4 = run >> 2, total = B * r4;
         constexpr int kMaxVec = kStripPixels * 3 / 4 / kBlockThreads;   // 6
         float v[kMaxVec][4];
@@ -276,6 +277,178 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
             }
             a.det[((size_t)s.f * d.H + s.row0 + r) * d.W + s.col0 + c] = o;
         }
+}
+
+// ---------------------------------------------------------------------------
+// K1, register variant for n <= 2: one thread per 2^n x 2^n block, the block
+// held in registers (no LDS, no barriers), the strip kernel's arithmetic in
+// the same order (so both give the same bits).  Each block row is a run of
+// 3 * 2^n stored values starting at a multiple of 2^n values: three vector
+// loads of 2^n values when the frames pointer is aligned to 2^n values.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ float half_bits(unsigned b);
+template <>
+__device__ __forceinline__ float half_bits<__half>(unsigned b) {
+    return __half2float(__ushort_as_half((unsigned short)b));
+}
+template <>
+__device__ __forceinline__ float half_bits<uint16_t>(unsigned b) {
+    return __uint_as_float(b << 16);  // bfloat16 -> float32 is exact
+}
+
+template <typename T, int BW>
+__device__ __forceinline__ void load_run(const T *p, float *v) {
+    if constexpr (std::is_same<T, float>::value) {
+        if constexpr (BW == 4) {
+            const float4 x = *reinterpret_cast<const float4 *>(p);
+            v[0] = x.x;
+            v[1] = x.y;
+            v[2] = x.z;
+            v[3] = x.w;
+        } else if constexpr (BW == 2) {
+            const float2 x = *reinterpret_cast<const float2 *>(p);
+            v[0] = x.x;
+            v[1] = x.y;
+        } else {
+            v[0] = p[0];
+        }
+    } else {
+        if constexpr (BW == 4) {
+            const uint2 x = *reinterpret_cast<const uint2 *>(p);
+            v[0] = half_bits<T>(x.x & 0xffffu);
+            v[1] = half_bits<T>(x.x >> 16);
+            v[2] = half_bits<T>(x.y & 0xffffu);
+            v[3] = half_bits<T>(x.y >> 16);
+        } else if constexpr (BW == 2) {
+            const unsigned x = *reinterpret_cast<const unsigned *>(p);
+            v[0] = half_bits<T>(x & 0xffffu);
+            v[1] = half_bits<T>(x >> 16);
+        } else {
+            v[0] = half_bits<T>(*reinterpret_cast<const unsigned short *>(p));
+        }
+    }
+}
+
+template <int BW>
+__device__ __forceinline__ void store_row(float2 *p, const float2 *o) {
+    if constexpr (BW == 4) {
+        reinterpret_cast<float4 *>(p)[0] = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
+        reinterpret_cast<float4 *>(p)[1] = make_float4(o[2].x, o[2].y, o[3].x, o[3].y);
+    } else if constexpr (BW == 2) {
+        reinterpret_cast<float4 *>(p)[0] = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
+    } else {
+        p[0] = o[0];
+    }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kBlockThreads) void k_log_haar_reg(const T *__restrict__ frames, HaarArgs a) {
+    constexpr int BW = 1 << N, NP = BW * BW;
+    const Dims &d = a.d;
+    const long long idx = (long long)blockIdx.x * kBlockThreads + threadIdx.x;
+    if (idx >= (long long)a.n_frames * d.LL) return;
+    const int f = (int)(idx / d.LL);
+    const long long q = idx - (long long)f * d.LL;
+    const int br = (int)(q / d.wl), bc = (int)(q - (long long)br * d.wl);
+    const int row0 = br << N, col0 = bc << N;
+    const T *__restrict__ base = frames + ((size_t)f * d.H * d.W + (size_t)row0 * d.W + col0) * 3;
+
+    // 1. Loads (all issued first), clamp.  I[k][r * BW + c].
+    float v[BW][3 * BW];
+#pragma unroll
+    for (int r = 0; r < BW; ++r)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) load_run<T, BW>(base + (size_t)r * d.W * 3 + t * BW, &v[r][t * BW]);
+    float I[3][NP], u[3][NP];
+#pragma unroll
+    for (int r = 0; r < BW; ++r)
+#pragma unroll
+        for (int e = 0; e < 3 * BW; ++e) {
+            const float x = v[r][e];
+            I[e % 3][r * BW + e / 3] = (x < a.floor) ? a.floor : x;  // NaN stays NaN
+        }
+
+    // 2. Block sum by the 2x2 cascade, block mean R.
+    float R[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) u[k][i] = I[k][i];
+#pragma unroll
+        for (int l = 1; l <= N; ++l) {
+            const int h = 1 << (l - 1), g2 = 2 * h;
+#pragma unroll
+            for (int r = 0; r < BW; r += g2)
+#pragma unroll
+                for (int c = 0; c < BW; c += g2)
+                    u[k][r * BW + c] = (u[k][r * BW + c] + u[k][r * BW + c + h]) +
+                                       (u[k][(r + h) * BW + c] + u[k][(r + h) * BW + c + h]);
+        }
+        R[k] = (N > 0) ? u[k][0] * (1.0f / (float)(1 << (2 * N))) : I[k][0];
+    }
+
+    // 3. Log-ratio to the block mean; 4. Haar in place (window * H, Eq. 1-2).
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) u[k][i] = -log1pf((I[k][i] - R[k]) / R[k]);
+#pragma unroll
+        for (int l = 1; l <= N; ++l) {
+            const int h = 1 << (l - 1), g2 = 2 * h;
+#pragma unroll
+            for (int r = 0; r < BW; r += g2)
+#pragma unroll
+                for (int c = 0; c < BW; c += g2) {
+                    const float w0 = u[k][r * BW + c], w1 = u[k][r * BW + c + h];
+                    const float w2 = u[k][(r + h) * BW + c], w3 = u[k][(r + h) * BW + c + h];
+                    u[k][r * BW + c] = 0.5f * ((w0 + w1) + (w2 + w3));
+                    u[k][(r + h) * BW + c] = 0.5f * ((w0 + w1) - (w2 + w3));
+                    u[k][(r + h) * BW + c + h] = 0.5f * ((w0 - w1) - (w2 - w3));
+                    u[k][r * BW + c + h] = 0.5f * ((w0 - w1) + (w2 - w3));
+                }
+        }
+    }
+
+    // 5. Centred low-pass observation (double-float), optionally projected.
+    const float invB = 1.0f / (float)BW;
+    float zh[3], zl[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        ln_ratio_df(a.iref[k], R[k], zh[k], zl[k]);
+        df_add(zh[k], zl[k], u[k][0] * invB);
+    }
+    if (a.project) {
+        float sh = zh[0], sl = zl[0];
+        df_add2(sh, sl, zh[1], zl[1]);
+        df_add2(sh, sl, zh[2], zl[2]);
+        const float mh = sh * (1.0f / 3.0f);
+        const float ml = (fmaf(-3.0f, mh, sh) + sl) * (1.0f / 3.0f);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) df_add2(zh[k], zl[k], -mh, -ml);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a.z[((size_t)f * 6 + k) * d.LL + q] = zh[k];
+        a.z[((size_t)f * 6 + 3 + k) * d.LL + q] = zl[k];
+    }
+
+    // 6. Tikhonov on the directional coefficients, block rows as vector stores.
+    const float m0 = a.M[0], m1 = a.M[1], m2 = a.M[2], m3 = a.M[3], m4 = a.M[4], m5 = a.M[5];
+#pragma unroll
+    for (int r = 0; r < BW; ++r) {
+        float2 o[BW];
+#pragma unroll
+        for (int c = 0; c < BW; ++c) {
+            o[c] = make_float2(0.0f, 0.0f);
+            if ((r | c) != 0) {
+                const float d0 = u[0][r * BW + c], d1 = u[1][r * BW + c], d2 = u[2][r * BW + c];
+                o[c].x = fmaf(m0, d0, fmaf(m1, d1, m2 * d2));
+                o[c].y = fmaf(m3, d0, fmaf(m4, d1, m5 * d2));
+            }
+        }
+        store_row<BW>(a.det + ((size_t)f * d.H + row0 + r) * d.W + col0, o);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -934,22 +1107,41 @@ hipError_t launch_tikhonov_fp64(const double *d_in, double *d_out, float *d_mf, 
     return hipGetLastError();
 }
 
+namespace {
+
+template <typename T, int N>
+void launch_reg(const void *frames, const HaarArgs &b, long long blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_log_haar_reg<T, N>), dim3((unsigned)blocks), dim3(kBlockThreads), 0, s,
+                       (const T *)frames, b);
+}
+
+template <typename T>
+void launch_k1(const void *frames, const HaarArgs &b, hipStream_t s) {
+    const int n = b.d.levels;
+    const bool aligned = ((uintptr_t)frames % ((size_t)(1 << n) * sizeof(T))) == 0;
+    HaarArgs c = b;
+    c.vec4 = ((uintptr_t)frames % (4 * sizeof(T))) == 0;
+    if (n <= 2 && aligned) {
+        const long long blocks = ((long long)b.n_frames * b.d.LL + kBlockThreads - 1) / kBlockThreads;
+        if (n == 0) launch_reg<T, 0>(frames, b, blocks, s);
+        else if (n == 1) launch_reg<T, 1>(frames, b, blocks, s);
+        else launch_reg<T, 2>(frames, b, blocks, s);
+    } else {
+        const long long grid = (long long)b.n_frames * b.d.hl * b.d.strips_per_row;
+        hipLaunchKernelGGL(k_log_haar<T>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, (const T *)frames, c);
+    }
+}
+
+}  // namespace
+
 hipError_t launch_log_haar(const void *frames, int n_frames, const HaarArgs &a, hipStream_t s) {
-    const long long grid = (long long)n_frames * a.d.hl * a.d.strips_per_row;
-    if (grid <= 0) return hipSuccess;
+    if (n_frames <= 0) return hipSuccess;
+    HaarArgs b = a;
+    b.n_frames = n_frames;
     switch (a.dtype) {
-        case HB_F32:
-            hipLaunchKernelGGL(k_log_haar<float>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s,
-                               (const float *)frames, a);
-            break;
-        case HB_F16:
-            hipLaunchKernelGGL(k_log_haar<__half>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s,
-                               (const __half *)frames, a);
-            break;
-        default:
-            hipLaunchKernelGGL(k_log_haar<uint16_t>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s,
-                               (const uint16_t *)frames, a);
-            break;
+        case HB_F32: launch_k1<float>(frames, b, s); break;
+        case HB_F16: launch_k1<__half>(frames, b, s); break;
+        default: launch_k1<uint16_t>(frames, b, s); break;
     }
     return hipGetLastError();
 }

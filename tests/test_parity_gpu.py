@@ -338,3 +338,35 @@ def test_posterior_tolerance_skips_within_its_bound(torch_cuda, tol):
     assert work[tol] < work[0.0]
     if bound <= 1e-5:
         hbtest.assert_maps_close(out[tol], hbtest.run_oracle(fr[None], "f32", s), f"tolerance {tol}")
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_register_and_strip_haar_kernels_agree_bitwise(torch_cuda, levels, dtype):
+    """For up to two levels the log + Haar step runs one block per thread in
+    registers when the frames pointer is aligned to a block row's vector
+    width; a frames pointer offset by one stored value takes the LDS strip
+    kernel with scalar loads.  Both follow the same arithmetic: the maps, the
+    low-pass observation and the details agree bit for bit."""
+    torch = torch_cuda
+    fr, _, _ = synth.single_frame(64, 96, config=77, dtype=dtype)
+    frames = fr[None]
+    s = _settings(levels=levels, grid=32)
+    run = hbtest.GpuRun(96, 64, s, dtype=dtype)
+    host = frames.view(np.int16) if dtype == "bf16" else frames
+    flat = torch.from_numpy(np.ascontiguousarray(host).reshape(-1))
+    aligned = flat.cuda()
+    padded = torch.empty(flat.numel() + 1, dtype=flat.dtype, device="cuda")
+    padded[1:] = aligned
+    offset = padded[1:].view(frames.shape)
+    outs = []
+    for src in (aligned.view(frames.shape), offset):
+        maps = [torch.full((1, 64, 96), float("nan"), device="cuda") for _ in range(4)]
+        run.plan.estimate(src, maps)
+        torch.cuda.synchronize()
+        outs.append((np.stack([m.cpu().numpy() for m in maps]),
+                     run.debug(run.hb.HB_DEBUG_LOWPASS_OBS), run.debug(run.hb.HB_DEBUG_DETAILS)))
+    for x, y in zip(outs[0], outs[1]):
+        assert np.array_equal(x, y, equal_nan=True)
+    hbtest.assert_maps_close(outs[0][0].transpose(1, 0, 2, 3), hbtest.run_oracle(frames, dtype, s), "register K1")
+    run.close()
