@@ -27,9 +27,14 @@ namespace hb {
 //     Slots outside the grid hold kPadCoord coordinates and kPadLogit here.
 //     [64 + j]: Hb of node j minus header[6]     [80 + j]: HbO2 minus header[7]
 //     [96..98] chunk box lower corner, [99..101] upper corner (relative)
-// The first 64 floats of a chunk are exactly the B operand of a 16x16x4 MFMA
-// (lane l reads float l: row k = l / 16, column j = l % 16); the A operand
-// carries twice the pixel's relative coordinates.
+//     [104 + 4 a + (0..3)], a = 0..3: for the chunk row of THb offset a,
+//       Hb = A_h + B_h s and HbO2 = A_o + B_o s at SO2 offset s = 0..3
+//       (exact on a product grid: THb is constant along the row and SO2 is
+//       linear in s), as (A_h, B_h, A_o, B_o) relative to header[6], [7].
+// The first 64 floats of a chunk are exactly the A operand of a 16x16x4 MFMA
+// (lane l reads float l: node row i = l % 16, column k = l / 16); the B
+// operand carries twice the pixel's relative coordinates, so lane l of the
+// result holds pixel l % 16 and the four nodes of chunk row l / 16.
 // Precision rule for the MFMA kernel.  Its expanded logit rounds at the scale
 // of the squared super-tile radius R^2 (scaled units), and a coarse grid
 // (node spacing h in uM of Hb/HbO2) turns a logit error into an estimate error
@@ -52,7 +57,7 @@ constexpr int kChunkNodes = 16;
 constexpr int kSupHdr = 32;
 constexpr int kMaxProbes = 16;
 constexpr int kProbeFloats = 8;
-constexpr int kChunkFloats = 104;
+constexpr int kChunkFloats = 120;
 constexpr float kPadLogit = -1.0e30f;
 // Coordinates of slots outside the grid: far from every observation (weight
 // exactly 0 in the difference form) yet small enough for the MFMA operands.

@@ -485,12 +485,12 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
     s = t;
 }
 
-// Sum over the 16 lanes of a row (lanes l ^ 8, 4, 2, 1), each pairwise step
-// exact up to a carried error term (two-sum), the error added at the end.
-__device__ __forceinline__ float lane_sum16(float x) {
+// Sum over the four lanes l, l ^ 16, l ^ 32, l ^ 48, each pairwise step exact
+// up to a carried error term (two-sum), the error added at the end.
+__device__ __forceinline__ float lane_sum_rows(float x) {
     float e = 0.0f;
 #pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) {
+    for (int o = 16; o <= 32; o <<= 1) {
         const float y = __shfl_xor(x, o), ye = __shfl_xor(e, o);
         float s, err;
         two_sum(x, y, s, err);
@@ -773,11 +773,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_reference(PosteriorArgs a) {
 
 // MFMA kernel: a wave takes PB blocks of 16 LL pixels.  Per super-tile and
 // 16-node chunk one v_mfma_f32_16x16x4_f32 forms the 16 x 16 logits
-//   t - m = [2 r, 1] . [v_g, -|v_g|^2] + (-(|r|^2 + m)),
-// whose per-pixel constant (the accumulator input) comes from one more MFMA
-// of [r0^2, r1^2, r2^2, m] against -1 per super-tile.  Each lane then holds 4
-// pixels x 1 node of the result (lane l: node l % 16, pixels 4 (l / 16) + q)
-// and runs the exponentials and the three moments on the VALU.
+//   t - m = [v_g, -|v_g|^2] . [2 r, 1] + (-(|r|^2 + m))
+// (nodes as rows, pixels as columns), whose per-pixel constant (the
+// accumulator input) comes from one more MFMA of -1 against
+// [r0^2, r1^2, r2^2, m] per super-tile.  Each lane then holds 1 pixel x the 4
+// nodes of one chunk row (lane l: pixel l % 16, THb row l / 16, SO2 offsets
+// 0..3) and runs the exponentials and the moments on the VALU.
 template <int PB>
 __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
     constexpr int PW = 16 * PB;
@@ -801,7 +802,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
     wave_obs_box(ph, pl, zlo, zhi);
     const PixelRef ref = pixel_reference<PW, LPP>(a, w, ph, pl, part, zlo, zhi);
 
-    // A operand of block b: lane (lp, lk) holds coordinate lk of pixel b*16 + lp
+    // B operand of block b: lane (lp, lk) holds coordinate lk of pixel b*16 + lp
     // (lk == 3: the homogeneous 1, and m for the constant term).
     float ah[PB], al[PB], am[PB];
 #pragma unroll
@@ -811,20 +812,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
         load_obs(zf, a.LL, p, lk < 3 ? lk : 0, sc, ah[b], al[b]);
         am[b] = __shfl(ref.m, b * 16 + lp);
     }
-    // Accumulator layout: lane (lp, lk) holds pixels b*16 + 4*lk + q, node lp.
-    float anc_hb[PB][4], anc_ox[PB][4];
+    // Result layout: lane (lp, lk) holds pixel b*16 + lp and the four nodes
+    // of chunk row lk; its sums run over those nodes of every kept chunk.
+    float anc_hb[PB], anc_ox[PB], R0[PB], R1[PB], R2[PB];
 #pragma unroll
-    for (int b = 0; b < PB; ++b)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            anc_hb[b][q] = __shfl(ref.ahb, b * 16 + 4 * lk + q);
-            anc_ox[b][q] = __shfl(ref.aox, b * 16 + 4 * lk + q);
-        }
-    float R0[PB][4], R1[PB][4], R2[PB][4];
-#pragma unroll
-    for (int b = 0; b < PB; ++b)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) R0[b][q] = R1[b][q] = R2[b][q] = 0.0f;
+    for (int b = 0; b < PB; ++b) {
+        anc_hb[b] = __shfl(ref.ahb, b * 16 + lp);
+        anc_ox[b] = __shfl(ref.aox, b * 16 + lp);
+        R0[b] = R1[b] = R2[b] = 0.0f;
+    }
 
     // Skipping.  A chunk (or super-tile) whose logit upper bound lies more
     // than skip_log2 below every pixel's reference has every weight below
@@ -862,13 +858,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
             const float r = (ah[b] - ch) + (al[b] - cl);
             av[b] = lk < 3 ? 2.0f * r : 1.0f;
             const float a2 = lk < 3 ? r * r : am[b];
-            cv[b] = mfma_16x16x4(a2, -1.0f, zero4);   // -(|r|^2 + m) per pixel row
+            cv[b] = mfma_16x16x4(-1.0f, a2, zero4);   // -(|r|^2 + m) per pixel column
         }
-        float L0[PB][4], L1[PB][4], L2[PB][4];
+        float L0[PB], L1[PB], L2[PB];
 #pragma unroll
-        for (int b = 0; b < PB; ++b)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) L0[b][q] = L1[b][q] = L2[b][q] = 0.0f;
+        for (int b = 0; b < PB; ++b) L0[b] = L1[b] = L2[b] = 0.0f;
         const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
         for (int cg = 0; cg < a.chunks_per_super; cg += 64) {
             const int ct = min(cg + lane, a.chunks_per_super - 1);
@@ -882,85 +876,82 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
             // loaded again), so the wait counts match on every path and a
             // wait for the current chunk never waits for the next one.
             int last = cg;
-            auto take = [&](float &bv, float &mh, float &mo) -> bool {
+            auto take = [&](float &bv, float4 &qm) -> bool {
                 const bool got = mask != 0;
                 last = got ? cg + __builtin_ctzll(mask | (1ull << 63)) : last;
                 mask &= mask - 1;
                 const float *__restrict__ C = C0 + (size_t)last * kChunkFloats;
                 bv = C[lane];
-                mh = C[64 + lp];
-                mo = C[80 + lp];
+                qm = *reinterpret_cast<const float4 *>(C + 104 + 4 * lk);
                 // keep these loads ahead of the evaluation that follows
                 __builtin_amdgcn_sched_barrier(0);
                 return got;
             };
-            auto eval = [&](float bv, float mh, float mo) {
+            // Weights of the row's four nodes (SO2 offsets s = 0..3): their sum
+            // W0 and first moment W1 = sum s w_s give the row's Hb and HbO2
+            // moments through the affine row coefficients.
+            auto eval = [&](float bv, const float4 &qm) {
                 ++executed;
 #pragma unroll
                 for (int b = 0; b < PB; ++b) {
-                    const f32x4 d = mfma_16x16x4(av[b], bv, cv[b]);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const float wt = __builtin_amdgcn_exp2f(d[q]);
-                        L0[b][q] += wt;
-                        L1[b][q] = fmaf(wt, mh, L1[b][q]);
-                        L2[b][q] = fmaf(wt, mo, L2[b][q]);
-                    }
+                    const f32x4 d = mfma_16x16x4(bv, av[b], cv[b]);
+                    const float w0 = __builtin_amdgcn_exp2f(d[0]), w1 = __builtin_amdgcn_exp2f(d[1]);
+                    const float w2 = __builtin_amdgcn_exp2f(d[2]), w3 = __builtin_amdgcn_exp2f(d[3]);
+                    const float W0 = (w0 + w1) + (w2 + w3);
+                    const float W1 = fmaf(3.0f, w3, fmaf(2.0f, w2, w1));
+                    L0[b] += W0;
+                    L1[b] = fmaf(qm.x, W0, fmaf(qm.y, W1, L1[b]));
+                    L2[b] = fmaf(qm.z, W0, fmaf(qm.w, W1, L2[b]));
                 }
             };
-            float bA, mhA, moA, bB, mhB, moB;
-            take(bA, mhA, moA);
+            float bA, bB;
+            float4 qA, qB;
+            take(bA, qA);
             while (true) {
-                const bool gotB = take(bB, mhB, moB);
-                eval(bA, mhA, moA);
+                const bool gotB = take(bB, qB);
+                eval(bA, qA);
                 if (!gotB) break;
-                const bool gotA = take(bA, mhA, moA);
-                eval(bB, mhB, moB);
+                const bool gotA = take(bA, qA);
+                eval(bB, qB);
                 if (!gotA) break;
             }
         }
         const float chb = T[6], cox = T[7];
 #pragma unroll
-        for (int b = 0; b < PB; ++b)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                R0[b][q] += L0[b][q];
-                R1[b][q] += fmaf(chb - anc_hb[b][q], L0[b][q], L1[b][q]);
-                R2[b][q] += fmaf(cox - anc_ox[b][q], L0[b][q], L2[b][q]);
-            }
+        for (int b = 0; b < PB; ++b) {
+            R0[b] += L0[b];
+            R1[b] += fmaf(chb - anc_hb[b], L0[b], L1[b]);
+            R2[b] += fmaf(cox - anc_ox[b], L0[b], L2[b]);
+        }
       }
     }
 
     if (a.work && lane == 0) atomicAdd(a.work, (unsigned long long)executed * PW * kChunkNodes);
 
-    // Reduce over the 16 node lanes of each row with compensated (two-sum)
-    // pairwise steps, then lanes with lp == 0 write.
+    // Reduce over the four chunk-row lanes of each pixel with compensated
+    // (two-sum) pairwise steps, then lanes with lk == 0 write.
 #pragma unroll
-    for (int b = 0; b < PB; ++b)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            R0[b][q] = lane_sum16(R0[b][q]);
-            R1[b][q] = lane_sum16(R1[b][q]);
-            R2[b][q] = lane_sum16(R2[b][q]);
-        }
+    for (int b = 0; b < PB; ++b) {
+        R0[b] = lane_sum_rows(R0[b]);
+        R1[b] = lane_sum_rows(R1[b]);
+        R2[b] = lane_sum_rows(R2[b]);
+    }
     float *out = a.part + ((size_t)w.f * a.split + w.split) * kPartFields * a.LL;
 #pragma unroll
-    for (int b = 0; b < PB; ++b)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int src = b * 16 + 4 * lk + q;
-            const float m = __shfl(ref.m, src);
-            long long p;
-            const bool valid = wave_pixel(a, w, src, p);
-            if (lp == 0 && valid) {
-                out[p] = m;
-                out[a.LL + p] = R0[b][q];
-                out[2 * a.LL + p] = R1[b][q];
-                out[3 * a.LL + p] = R2[b][q];
-                out[4 * a.LL + p] = anc_hb[b][q];
-                out[5 * a.LL + p] = anc_ox[b][q];
-            }
+    for (int b = 0; b < PB; ++b) {
+        const int src = b * 16 + lp;
+        const float m = __shfl(ref.m, src);
+        long long p;
+        const bool valid = wave_pixel(a, w, src, p);
+        if (lk == 0 && valid) {
+            out[p] = m;
+            out[a.LL + p] = R0[b];
+            out[2 * a.LL + p] = R1[b];
+            out[3 * a.LL + p] = R2[b];
+            out[4 * a.LL + p] = anc_hb[b];
+            out[5 * a.LL + p] = anc_ox[b];
         }
+    }
 }
 
 // Direct kernel: one LL pixel per lane, logits in the difference form

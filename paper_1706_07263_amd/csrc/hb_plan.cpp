@@ -258,6 +258,24 @@ double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const doubl
                         blo[k] = std::min(blo[k], clo[k]);
                         bhi[k] = std::max(bhi[k], chi[k]);
                     }
+                    // row moments: Hb and HbO2 along each THb row are affine in
+                    // the SO2 offset (THb fixed, SO2 a linspace)
+                    const double dso2 = GS > 1 ? (d.so2_max - d.so2_min) / (GS - 1) : 0.0;
+                    for (int ra = 0; ra < 4; ++ra) {
+                        float *Q = C + 104 + 4 * ra;
+                        const int ga = a0 + 4 * ca + ra;
+                        if (ga >= GT) {
+                            Q[0] = Q[1] = Q[2] = Q[3] = 0.0f;
+                            continue;
+                        }
+                        const double thb = lin(d.thb_min, d.thb_max, GT, ga);
+                        const double so2 = lin(d.so2_min, d.so2_max, GS, b0 + 4 * cs);
+                        Q[0] = (float)(thb * (1.0 - so2) - (double)chb_c);
+                        Q[1] = (float)(-thb * dso2);
+                        Q[2] = (float)(thb * so2 - (double)cox_c);
+                        Q[3] = (float)(thb * dso2);
+                    }
+                    for (int k = 102; k < 104; ++k) C[k] = 0.0f;
                 }
             // probes: the middle real node of each 8 x 8 patch
             int np = 0;
