@@ -779,8 +779,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_reference(PosteriorArgs a) {
 // [r0^2, r1^2, r2^2, m] per super-tile.  Each lane then holds 1 pixel x the 4
 // nodes of one chunk row (lane l: pixel l % 16, THb row l / 16, SO2 offsets
 // 0..3) and runs the exponentials and the moments on the VALU.
+// Seven waves per SIMD (72 VGPRs; a few values spill outside the chunk loop)
+// measured fastest: 6 and 8 were slower on the 1080p workload.
 template <int PB>
-__global__ __launch_bounds__(kBlockThreads) void k_posterior(PosteriorArgs a) {
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_posterior(PosteriorArgs a) {
     constexpr int PW = 16 * PB;
     constexpr int LPP = 64 / PW;
     const int lane = threadIdx.x & 63;
