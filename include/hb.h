@@ -185,11 +185,10 @@ hb_status_t hb_plan_get_work(hb_plan_t plan, int64_t *evaluated, int64_t *full);
  *       z_k = ybar_k - mu_ref_k (ybar = block mean of log-attenuation) as a
  *       double-float: z_k = [0][k] + [1][k] (high and low parts),
  *       LL = (height >> levels) * (width >> levels), row-major blocks;
- *   HB_DEBUG_DETAILS: float32 [height][width][2], Tikhonov-inverted
- *       directional coefficients (Hb, HbO2) in the in-place Haar layout: the
- *       level-l coefficients of the 2^l block at (r, c) sit at (r, c + h)
- *       (column difference), (r + h, c) (row difference), (r + h, c + h)
- *       (diagonal) with h = 2^(l-1); the block's own corner holds 0;
+ *   HB_DEBUG_DETAILS: float32 [height][width][2], detail part of the maps
+ *       (Hb, HbO2): the inverse Haar (Eq. 4) of the Tikhonov-inverted
+ *       directional coefficients with the low-pass coefficient set to 0; the
+ *       maps are this plus the block's low-pass estimate;
  *   HB_DEBUG_LOWPASS_EST: float32 [LL][2], low-pass estimate (Hb, HbO2)
  *       per block (the block mean of the output maps). */
 typedef enum { HB_DEBUG_LOWPASS_OBS = 0, HB_DEBUG_DETAILS = 1, HB_DEBUG_LOWPASS_EST = 2 } hb_debug_buffer_t;

@@ -104,7 +104,7 @@ struct HaarArgs {
     float iref[3];           // float32 reference intensities exp(-mu_ref)
     const float *M;          // device, 6 floats (FP32 Tikhonov operator)
     float *z;                // [n][6][LL]: high parts R,G,B then low parts
-    float2 *det;             // [n][H][W]
+    float2 *det;             // [n][H][W] spatial detail part (inverse Haar of the details)
     int project;             // project z onto the plane orthogonal to (1,1,1)
 };
 
@@ -127,12 +127,13 @@ struct PosteriorArgs {
 
 struct RecomposeArgs {
     Dims d;
+    int n_frames;
     int lowpass;
     int split;
     const float *part;       // posterior partials
     const float *z;          // low-pass observation (Tikhonov low-pass)
     const float *M;          // device FP32 M (6) followed by the low-pass offset (2)
-    const float2 *det;
+    const float2 *det;       // [n][H][W] spatial detail part (inverse Haar of the details)
     float2 *est;             // [n][LL] low-pass estimate (side output)
     float thb_eps;
     float *hb, *hbo2, *thb, *so2;

@@ -284,18 +284,45 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
         }
     }
 
-    // 6. Tikhonov on every directional coefficient: (Hb, HbO2) = M * (R, G, B).
+    // 6. Tikhonov on every directional coefficient: (Hb, HbO2) = M * (R, G, B),
+    //    the low-pass slot set to 0 (s_i, read by step 5 when n = 0, then
+    //    holds the result).
+    __syncthreads();
     const float m0 = a.M[0], m1 = a.M[1], m2 = a.M[2], m3 = a.M[3], m4 = a.M[4], m5 = a.M[5];
     for (int r = 0; r < B; ++r)
         for (int c = tid; c < ncols; c += kBlockThreads) {
-            float2 o = make_float2(0.0f, 0.0f);
+            float ox = 0.0f, oy = 0.0f;
             if (((r | c) & (B - 1)) != 0) {
                 const float d0 = s_u[0][r * Wt + c], d1 = s_u[1][r * Wt + c], d2 = s_u[2][r * Wt + c];
-                o.x = fmaf(m0, d0, fmaf(m1, d1, m2 * d2));
-                o.y = fmaf(m3, d0, fmaf(m4, d1, m5 * d2));
+                ox = fmaf(m0, d0, fmaf(m1, d1, m2 * d2));
+                oy = fmaf(m3, d0, fmaf(m4, d1, m5 * d2));
             }
-            a.det[((size_t)s.f * d.H + s.row0 + r) * d.W + s.col0 + c] = o;
+            s_i[0][r * Wt + c] = ox;
+            s_i[1][r * Wt + c] = oy;
         }
+    __syncthreads();
+
+    // 7. Inverse Haar of the detail part (Eq. 4: window = coefficients * H,
+    //    levels n..1): the maps are this plus the block's low-pass estimate.
+    for (int l = n; l >= 1; --l) {
+        const int h = 1 << (l - 1), g2 = 2 * h, gc = ncols >> l;
+        for (int r = 0; r < B; r += g2)
+            for (int q = tid; q < gc * 2; q += kBlockThreads) {
+                const int k = q & 1, c = (q >> 1) * g2;
+                float *u = s_i[k];
+                const float ll = u[r * Wt + c], d1 = u[(r + h) * Wt + c];
+                const float d2 = u[(r + h) * Wt + c + h], d3 = u[r * Wt + c + h];
+                u[r * Wt + c] = 0.5f * ((ll + d1) + (d2 + d3));
+                u[r * Wt + c + h] = 0.5f * ((ll + d1) - (d2 + d3));
+                u[(r + h) * Wt + c] = 0.5f * ((ll - d1) - (d2 - d3));
+                u[(r + h) * Wt + c + h] = 0.5f * ((ll - d1) + (d2 - d3));
+            }
+        __syncthreads();
+    }
+    for (int r = 0; r < B; ++r)
+        for (int c = tid; c < ncols; c += kBlockThreads)
+            a.det[((size_t)s.f * d.H + s.row0 + r) * d.W + s.col0 + c] =
+                make_float2(s_i[0][r * Wt + c], s_i[1][r * Wt + c]);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,21 +480,42 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar_reg(const T *__restr
         a.z[((size_t)f * 6 + 3 + k) * d.LL + q] = zl[k];
     }
 
-    // 6. Tikhonov on the directional coefficients, block rows as vector stores.
+    // 6. Tikhonov on the directional coefficients (low-pass slot 0); 7. the
+    //    inverse Haar of this detail part; block rows as vector stores.
     const float m0 = a.M[0], m1 = a.M[1], m2 = a.M[2], m3 = a.M[3], m4 = a.M[4], m5 = a.M[5];
+    float o[2][NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        o[0][i] = o[1][i] = 0.0f;
+        if (i != 0) {
+            const float d0 = u[0][i], d1 = u[1][i], d2 = u[2][i];
+            o[0][i] = fmaf(m0, d0, fmaf(m1, d1, m2 * d2));
+            o[1][i] = fmaf(m3, d0, fmaf(m4, d1, m5 * d2));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int l = N; l >= 1; --l) {
+            const int h = 1 << (l - 1), g2 = 2 * h;
+#pragma unroll
+            for (int r = 0; r < BW; r += g2)
+#pragma unroll
+                for (int c = 0; c < BW; c += g2) {
+                    const float ll = o[k][r * BW + c], d1 = o[k][(r + h) * BW + c];
+                    const float d2 = o[k][(r + h) * BW + c + h], d3 = o[k][r * BW + c + h];
+                    o[k][r * BW + c] = 0.5f * ((ll + d1) + (d2 + d3));
+                    o[k][r * BW + c + h] = 0.5f * ((ll + d1) - (d2 + d3));
+                    o[k][(r + h) * BW + c] = 0.5f * ((ll - d1) - (d2 - d3));
+                    o[k][(r + h) * BW + c + h] = 0.5f * ((ll - d1) + (d2 - d3));
+                }
+        }
 #pragma unroll
     for (int r = 0; r < BW; ++r) {
-        float2 o[BW];
+        float2 row[BW];
 #pragma unroll
-        for (int c = 0; c < BW; ++c) {
-            o[c] = make_float2(0.0f, 0.0f);
-            if ((r | c) != 0) {
-                const float d0 = u[0][r * BW + c], d1 = u[1][r * BW + c], d2 = u[2][r * BW + c];
-                o[c].x = fmaf(m0, d0, fmaf(m1, d1, m2 * d2));
-                o[c].y = fmaf(m3, d0, fmaf(m4, d1, m5 * d2));
-            }
-        }
-        store_row<BW>(a.det + ((size_t)f * d.H + row0 + r) * d.W + col0, o);
+        for (int c = 0; c < BW; ++c) row[c] = make_float2(o[0][r * BW + c], o[1][r * BW + c]);
+        store_row<BW>(a.det + ((size_t)f * d.H + row0 + r) * d.W + col0, row);
     }
 }
 
@@ -1059,57 +1107,68 @@ __device__ __forceinline__ float2 lowpass_estimate(const RecomposeArgs &a, int f
     return make_float2(a_hb + s1 / s0, a_ox + s2 / s0);
 }
 
+// Maps of V consecutive pixels from their detail part and the block's
+// low-pass estimate; vector stores when V > 1 (the host checks alignment).
+template <int V>
+__device__ __forceinline__ void write_maps(const RecomposeArgs &a, size_t o, float2 e, const float2 *dp) {
+    float hb[V], ox[V], th[V], so[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        hb[i] = e.x + dp[i].x;
+        ox[i] = e.y + dp[i].y;
+        th[i] = hb[i] + ox[i];
+        so[i] = (th[i] > a.thb_eps) ? ox[i] / th[i] : __builtin_nanf("");
+    }
+    auto put = [&](float *m, const float *v) {
+        if (!m) return;
+        if constexpr (V == 4) {
+            *reinterpret_cast<float4 *>(m + o) = make_float4(v[0], v[1], v[2], v[3]);
+        } else if constexpr (V == 2) {
+            *reinterpret_cast<float2 *>(m + o) = make_float2(v[0], v[1]);
+        } else {
+            m[o] = v[0];
+        }
+    };
+    put(a.hb, hb);
+    put(a.hbo2, ox);
+    put(a.thb, th);
+    put(a.so2, so);
+}
+
+// K3: one thread per (frame, block, block row): the block's low-pass
+// estimate (split merge, or the Tikhonov low-pass), plus the row's detail
+// part, to the four maps, V pixels per vector access.
+template <int V>
 __global__ __launch_bounds__(kBlockThreads) void k_recompose(RecomposeArgs a) {
-    __shared__ float s_c[2][kStripPixels];
-    __shared__ float s_e[2][kStripPixels];
     const Dims &d = a.d;
-    const StripPos s = strip_pos(d);
-    const int n = d.levels, B = s.B, Wt = s.Wt, ncols = s.ncols;
-    const int tid = threadIdx.x;
-
-    for (int j = tid; j < s.nb; j += kBlockThreads) {
-        const long long q = (long long)s.br * d.wl + s.blk0 + j;
-        const float2 e = lowpass_estimate(a, s.f, q);
-        s_e[0][j] = e.x;
-        s_e[1][j] = e.y;
-        a.est[(size_t)s.f * d.LL + q] = e;
-    }
-    for (int r = 0; r < B; ++r)
-        for (int c = tid; c < ncols; c += kBlockThreads) {
-            const float2 v = a.det[((size_t)s.f * d.H + s.row0 + r) * d.W + s.col0 + c];
-            s_c[0][r * Wt + c] = v.x;
-            s_c[1][r * Wt + c] = v.y;
+    const int n = d.levels, B = 1 << n;
+    const long long idx = (long long)blockIdx.x * kBlockThreads + threadIdx.x;
+    if (idx >= (long long)a.n_frames * d.LL * B) return;
+    const long long blk = idx >> n;
+    const int r = (int)(idx & (B - 1));
+    const int f = (int)(blk / d.LL);
+    const long long q = blk - (long long)f * d.LL;
+    const int br = (int)(q / d.wl), bc = (int)(q - (long long)br * d.wl);
+    const float2 e = lowpass_estimate(a, f, q);
+    if (r == 0) a.est[(size_t)f * d.LL + q] = e;
+    const size_t row = ((size_t)f * d.H + ((size_t)br << n) + r) * d.W + ((size_t)bc << n);
+    for (int c = 0; c < B; c += V) {
+        float2 dp[V];
+        if constexpr (V == 4) {
+            const float4 x = *reinterpret_cast<const float4 *>(a.det + row + c);
+            const float4 y = *reinterpret_cast<const float4 *>(a.det + row + c + 2);
+            dp[0] = make_float2(x.x, x.y);
+            dp[1] = make_float2(x.z, x.w);
+            dp[2] = make_float2(y.x, y.y);
+            dp[3] = make_float2(y.z, y.w);
+        } else if constexpr (V == 2) {
+            const float4 x = *reinterpret_cast<const float4 *>(a.det + row + c);
+            dp[0] = make_float2(x.x, x.y);
+            dp[1] = make_float2(x.z, x.w);
+        } else {
+            dp[0] = a.det[row + c];
         }
-    __syncthreads();
-
-    // Inverse Haar (Eq. 4): window = coefficients * H, levels n..1.
-    for (int l = n; l >= 1; --l) {
-        const int h = 1 << (l - 1), g2 = 2 * h, gc = ncols >> l;
-        for (int r = 0; r < B; r += g2)
-        for (int q = tid; q < gc * 2; q += kBlockThreads) {
-            const int k = q & 1, c = (q >> 1) * g2;
-            float *u = s_c[k];
-            const float ll = u[r * Wt + c], d1 = u[(r + h) * Wt + c];
-            const float d2 = u[(r + h) * Wt + c + h], d3 = u[r * Wt + c + h];
-            u[r * Wt + c] = 0.5f * ((ll + d1) + (d2 + d3));
-            u[r * Wt + c + h] = 0.5f * ((ll + d1) - (d2 + d3));
-            u[(r + h) * Wt + c] = 0.5f * ((ll - d1) - (d2 - d3));
-            u[(r + h) * Wt + c + h] = 0.5f * ((ll - d1) + (d2 - d3));
-        }
-        __syncthreads();
-    }
-
-    for (int r = 0; r < B; ++r)
-    for (int c = tid; c < ncols; c += kBlockThreads) {
-        const int j = c >> n;
-        const float hb = s_e[0][j] + s_c[0][r * Wt + c];
-        const float hbo2 = s_e[1][j] + s_c[1][r * Wt + c];
-        const float thb = hb + hbo2;
-        const size_t o = ((size_t)s.f * d.H + s.row0 + r) * d.W + s.col0 + c;
-        if (a.hb) a.hb[o] = hb;
-        if (a.hbo2) a.hbo2[o] = hbo2;
-        if (a.thb) a.thb[o] = thb;
-        if (a.so2) a.so2[o] = (thb > a.thb_eps) ? hbo2 / thb : __builtin_nanf("");
+        write_maps<V>(a, row + c, e, dp);
     }
 }
 
@@ -1180,9 +1239,24 @@ hipError_t launch_posterior(const PosteriorArgs &a, bool mfma, hipStream_t s) {
 }
 
 hipError_t launch_recompose(int n_frames, const RecomposeArgs &a, hipStream_t s) {
-    const long long grid = (long long)n_frames * a.d.hl * a.d.strips_per_row;
-    if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_recompose, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
+    if (n_frames <= 0) return hipSuccess;
+    RecomposeArgs b = a;
+    b.n_frames = n_frames;
+    const int B = 1 << a.d.levels;
+    const long long blocks = ((long long)n_frames * a.d.LL * B + kBlockThreads - 1) / kBlockThreads;
+    // widest vector the block width and every map pointer allow
+    auto fits = [&](int v) {
+        if (B % v) return false;
+        for (const float *m : {a.hb, a.hbo2, a.thb, a.so2})
+            if (m && ((uintptr_t)m % (sizeof(float) * v)) != 0) return false;
+        return true;
+    };
+    if (fits(4))
+        hipLaunchKernelGGL(k_recompose<4>, dim3((unsigned)blocks), dim3(kBlockThreads), 0, s, b);
+    else if (fits(2))
+        hipLaunchKernelGGL(k_recompose<2>, dim3((unsigned)blocks), dim3(kBlockThreads), 0, s, b);
+    else
+        hipLaunchKernelGGL(k_recompose<1>, dim3((unsigned)blocks), dim3(kBlockThreads), 0, s, b);
     return hipGetLastError();
 }
 
