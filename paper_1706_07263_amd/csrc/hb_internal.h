@@ -123,6 +123,15 @@ struct PosteriorArgs {
     float *gref;             // [n][LL] best probe logit over the whole grid, or null (one split)
     float *part;             // [n][split][kPartFields][LL]
     unsigned long long *work;  // optional: pairs evaluated (pixel x node), added per wave
+    // Fused recomposition (one split, MFMA kernel, levels <= 2): the kernel
+    // writes the low-pass estimate and the maps itself instead of partials.
+    int fuse;
+    int levels, H, W;
+    int vec;                 // pixels per map store: 1, 2 or 4 (pointer alignment)
+    const float2 *det;       // [n][H][W] spatial detail part
+    float2 *est;             // [n][LL] low-pass estimate
+    float thb_eps;
+    float *hb, *hbo2, *thb, *so2;
 };
 
 struct RecomposeArgs {

@@ -519,6 +519,55 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar_reg(const T *__restr
     }
 }
 
+// Maps of V consecutive pixels (offset o) from their detail part and the
+// block's low-pass estimate e; vector stores when V > 1 (the host checks the
+// alignment of the map pointers).  Null maps are skipped.
+template <int V>
+__device__ __forceinline__ void write_maps(float *mhb, float *mox, float *mth, float *mso, float thb_eps, size_t o,
+                                           float2 e, const float2 *dp) {
+    float hb[V], ox[V], th[V], so[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        hb[i] = e.x + dp[i].x;
+        ox[i] = e.y + dp[i].y;
+        th[i] = hb[i] + ox[i];
+        so[i] = (th[i] > thb_eps) ? ox[i] / th[i] : __builtin_nanf("");
+    }
+    auto put = [&](float *m, const float *v) {
+        if (!m) return;
+        if constexpr (V == 4) {
+            *reinterpret_cast<float4 *>(m + o) = make_float4(v[0], v[1], v[2], v[3]);
+        } else if constexpr (V == 2) {
+            *reinterpret_cast<float2 *>(m + o) = make_float2(v[0], v[1]);
+        } else {
+            m[o] = v[0];
+        }
+    };
+    put(mhb, hb);
+    put(mox, ox);
+    put(mth, th);
+    put(mso, so);
+}
+
+// V consecutive detail-part values from offset o.
+template <int V>
+__device__ __forceinline__ void load_detail(const float2 *det, size_t o, float2 *dp) {
+    if constexpr (V == 4) {
+        const float4 x = *reinterpret_cast<const float4 *>(det + o);
+        const float4 y = *reinterpret_cast<const float4 *>(det + o + 2);
+        dp[0] = make_float2(x.x, x.y);
+        dp[1] = make_float2(x.z, x.w);
+        dp[2] = make_float2(y.x, y.y);
+        dp[3] = make_float2(y.z, y.w);
+    } else if constexpr (V == 2) {
+        const float4 x = *reinterpret_cast<const float4 *>(det + o);
+        dp[0] = make_float2(x.x, x.y);
+        dp[1] = make_float2(x.z, x.w);
+    } else {
+        dp[0] = det[o];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K2: posterior mean over the grid on the low-pass band.
 //
@@ -839,6 +888,52 @@ __global__ __launch_bounds__(kBlockThreads) void k_reference(PosteriorArgs a) {
     a.gref[i] = mlo;
 }
 
+// Fused recomposition for one split and n <= 2: every lane of pixel row lp
+// holds the pixel's complete sums after the lane reduction, so the estimate
+// is anchor + S1 / S0 (what the split merge gives for one split, bit for
+// bit).  The wave then writes the maps of its tile, (4 x 2^n) x (8 x 2^n)
+// pixels in units of V along a row: the unit's estimate is fetched from its
+// pixel's lanes (uniform trip count) before any lane branches.
+template <int PB, int V>
+__device__ __forceinline__ void fused_maps(const PosteriorArgs &a, const WaveWork &w, const float *anc_hb,
+                                           const float *anc_ox, const float *R0, const float *R1,
+                                           const float *R2) {
+    const int lane = threadIdx.x & 63;
+    const int lp = lane & 15, lk = lane >> 4;
+    const int n = a.levels, B = 1 << n;
+    float ex[PB], ey[PB];
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+        ex[b] = anc_hb[b] + R1[b] / R0[b];
+        ey[b] = anc_ox[b] + R2[b] / R0[b];
+        long long p;
+        if (lk == 0 && wave_pixel(a, w, b * 16 + lp, p)) a.est[(size_t)w.f * a.LL + p] = make_float2(ex[b], ey[b]);
+    }
+    const int per_row = (kWaveTileW * B) / V;             // units per tile row
+    const int n_units = (16 * PB / kWaveTileW) * B * per_row;
+    const int T = (n_units + 63) / 64;                     // same for every lane
+    for (int t = 0; t < T; ++t) {
+        const int u = lane + 64 * t;
+        const bool live = u < n_units;
+        const int y = live ? u / per_row : 0, x = live ? (u - y * per_row) * V : 0;
+        const int ty = y >> n, tx = x >> n;
+        const int i = ty * kWaveTileW + tx;                 // LL pixel of the tile
+        float2 e = make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const float sx = __shfl(ex[b], i & 15), sy = __shfl(ey[b], i & 15);
+            if ((i >> 4) == b) e = make_float2(sx, sy);
+        }
+        const int gr = w.r0 + ty, gc = w.c0 + tx;
+        if (!live || gr >= a.hl || gc >= a.wl) continue;
+        const size_t o = ((size_t)w.f * a.H + ((size_t)gr << n) + (y & (B - 1))) * a.W + ((size_t)gc << n) +
+                         (x & (B - 1));
+        float2 dp[V];
+        load_detail<V>(a.det, o, dp);
+        write_maps<V>(a.hb, a.hbo2, a.thb, a.so2, a.thb_eps, o, e, dp);
+    }
+}
+
 // MFMA kernel: a wave takes PB blocks of 16 LL pixels.  Per super-tile and
 // 16-node chunk one v_mfma_f32_16x16x4_f32 forms the 16 x 16 logits
 //   t - m = [v_g, -|v_g|^2] . [2 r, 1] + (-(|r|^2 + m))
@@ -1006,6 +1101,14 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(7
         R1[b] = lane_sum_rows(R1[b]);
         R2[b] = lane_sum_rows(R2[b]);
     }
+    if (a.fuse) {
+        switch (a.vec) {
+            case 4: fused_maps<PB, 4>(a, w, anc_hb, anc_ox, R0, R1, R2); break;
+            case 2: fused_maps<PB, 2>(a, w, anc_hb, anc_ox, R0, R1, R2); break;
+            default: fused_maps<PB, 1>(a, w, anc_hb, anc_ox, R0, R1, R2); break;
+        }
+        return;
+    }
     float *out = a.part + ((size_t)w.f * a.split + w.split) * kPartFields * a.LL;
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
@@ -1107,34 +1210,6 @@ __device__ __forceinline__ float2 lowpass_estimate(const RecomposeArgs &a, int f
     return make_float2(a_hb + s1 / s0, a_ox + s2 / s0);
 }
 
-// Maps of V consecutive pixels from their detail part and the block's
-// low-pass estimate; vector stores when V > 1 (the host checks alignment).
-template <int V>
-__device__ __forceinline__ void write_maps(const RecomposeArgs &a, size_t o, float2 e, const float2 *dp) {
-    float hb[V], ox[V], th[V], so[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-        hb[i] = e.x + dp[i].x;
-        ox[i] = e.y + dp[i].y;
-        th[i] = hb[i] + ox[i];
-        so[i] = (th[i] > a.thb_eps) ? ox[i] / th[i] : __builtin_nanf("");
-    }
-    auto put = [&](float *m, const float *v) {
-        if (!m) return;
-        if constexpr (V == 4) {
-            *reinterpret_cast<float4 *>(m + o) = make_float4(v[0], v[1], v[2], v[3]);
-        } else if constexpr (V == 2) {
-            *reinterpret_cast<float2 *>(m + o) = make_float2(v[0], v[1]);
-        } else {
-            m[o] = v[0];
-        }
-    };
-    put(a.hb, hb);
-    put(a.hbo2, ox);
-    put(a.thb, th);
-    put(a.so2, so);
-}
-
 // K3: one thread per (frame, block, block row): the block's low-pass
 // estimate (split merge, or the Tikhonov low-pass), plus the row's detail
 // part, to the four maps, V pixels per vector access.
@@ -1154,21 +1229,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_recompose(RecomposeArgs a) {
     const size_t row = ((size_t)f * d.H + ((size_t)br << n) + r) * d.W + ((size_t)bc << n);
     for (int c = 0; c < B; c += V) {
         float2 dp[V];
-        if constexpr (V == 4) {
-            const float4 x = *reinterpret_cast<const float4 *>(a.det + row + c);
-            const float4 y = *reinterpret_cast<const float4 *>(a.det + row + c + 2);
-            dp[0] = make_float2(x.x, x.y);
-            dp[1] = make_float2(x.z, x.w);
-            dp[2] = make_float2(y.x, y.y);
-            dp[3] = make_float2(y.z, y.w);
-        } else if constexpr (V == 2) {
-            const float4 x = *reinterpret_cast<const float4 *>(a.det + row + c);
-            dp[0] = make_float2(x.x, x.y);
-            dp[1] = make_float2(x.z, x.w);
-        } else {
-            dp[0] = a.det[row + c];
-        }
-        write_maps<V>(a, row + c, e, dp);
+        load_detail<V>(a.det, row + c, dp);
+        write_maps<V>(a.hb, a.hbo2, a.thb, a.so2, a.thb_eps, row + c, e, dp);
     }
 }
 

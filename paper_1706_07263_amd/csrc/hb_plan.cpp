@@ -557,6 +557,7 @@ hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_fram
     if (mark(0) != hipSuccess) return HB_ERR_DEVICE;
     if (launch_log_haar(d_frames, n_frames, ha, s) != hipSuccess) return HB_ERR_DEVICE;
     if (mark(1) != hipSuccess) return HB_ERR_DEVICE;
+    bool fused = false;
     if (p->desc.lowpass == HB_LOWPASS_BAYES) {
         PosteriorArgs pa{};
         pa.LL = p->dims.LL;
@@ -578,6 +579,29 @@ hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_fram
             pa.gref = p->d_gref;
             if (launch_reference(pa, s) != hipSuccess) return HB_ERR_DEVICE;
         }
+        // One split, MFMA kernel, n <= 2: the posterior writes the maps.
+        fused = p->use_mfma && p->split == 1 && p->dims.levels <= 2;
+        if (fused) {
+            const int B = 1 << p->dims.levels;
+            auto fits = [&](int v) {
+                if (B % v) return false;
+                for (const float *m : {d_out->hb, d_out->hbo2, d_out->thb, d_out->so2})
+                    if (m && ((uintptr_t)m % (sizeof(float) * v)) != 0) return false;
+                return true;
+            };
+            pa.fuse = 1;
+            pa.vec = fits(4) ? 4 : (fits(2) ? 2 : 1);
+            pa.levels = p->dims.levels;
+            pa.H = p->dims.H;
+            pa.W = p->dims.W;
+            pa.det = p->d_det;
+            pa.est = p->d_est;
+            pa.thb_eps = (float)p->desc.thb_eps;
+            pa.hb = d_out->hb;
+            pa.hbo2 = d_out->hbo2;
+            pa.thb = d_out->thb;
+            pa.so2 = d_out->so2;
+        }
         if (launch_posterior(pa, p->use_mfma, s) != hipSuccess) return HB_ERR_DEVICE;
     }
     if (mark(2) != hipSuccess) return HB_ERR_DEVICE;
@@ -595,7 +619,7 @@ hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_fram
     ra.hbo2 = d_out->hbo2;
     ra.thb = d_out->thb;
     ra.so2 = d_out->so2;
-    if (launch_recompose(n_frames, ra, s) != hipSuccess) return HB_ERR_DEVICE;
+    if (!fused && launch_recompose(n_frames, ra, s) != hipSuccess) return HB_ERR_DEVICE;
     if (mark(3) != hipSuccess) return HB_ERR_DEVICE;
     p->last_frames = n_frames;
     return HB_OK;

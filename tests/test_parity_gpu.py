@@ -371,3 +371,42 @@ def test_register_and_strip_haar_kernels_agree_bitwise(torch_cuda, levels, dtype
         assert np.array_equal(x, y, equal_nan=True)
     hbtest.assert_maps_close(outs[0][0].transpose(1, 0, 2, 3), hbtest.run_oracle(frames, dtype, s), "register K1")
     run.close()
+
+
+@pytest.mark.parametrize("h,w,levels,split,offset", [
+    (64, 96, 2, 1, 0),      # one split: the posterior kernel writes the maps
+    (40, 72, 2, 1, 0),      # ragged wave tiles
+    (96, 200, 1, 1, 0),
+    (8, 3000, 0, 1, 0),
+    (64, 96, 2, 1, 1),      # map pointers off 16-byte alignment: scalar stores
+    (64, 96, 2, 3, 0),      # split grid: the recomposition kernel writes them
+    (32, 96, 3, 1, 0),      # three levels: recomposition kernel
+])
+def test_maps_are_estimate_plus_detail_part(torch_cuda, h, w, levels, split, offset):
+    """Bit for bit, on every path that writes the maps: Hb and HbO2 are the
+    block's low-pass estimate plus the detail part, THb their sum, SO2 their
+    ratio (NaN at THb <= thb_eps); and the maps match the oracle."""
+    torch = torch_cuda
+    fr, _, _ = synth.single_frame(h, w, config=81)
+    s = _settings(levels=levels, grid=(24 if levels == 0 else 32))
+    run = hbtest.GpuRun(w, h, s, grid_split=split)
+    assert run.plan.info()["grid_split"] == split
+    src = hbtest.to_device(fr[None], "f32")
+    buf = torch.full((4, h * w + offset), float("nan"), device="cuda")
+    maps = [buf[k, offset:].view(1, h, w) for k in range(4)]
+    run.plan.estimate(src, maps)
+    torch.cuda.synchronize()
+    out = np.stack([m.cpu().numpy() for m in maps])[:, 0]
+    est = run.debug(run.hb.HB_DEBUG_LOWPASS_EST).reshape(h >> levels, w >> levels, 2)
+    det = run.debug(run.hb.HB_DEBUG_DETAILS)
+    b = 1 << levels
+    e = np.repeat(np.repeat(est, b, axis=0), b, axis=1)
+    hb = (e[..., 0] + det[..., 0]).astype(np.float32)
+    ox = (e[..., 1] + det[..., 1]).astype(np.float32)
+    th = (hb + ox).astype(np.float32)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        so = np.where(th > np.float32(1e-3), ox / th, np.float32(np.nan)).astype(np.float32)
+    for k, want in enumerate((hb, ox, th, so)):
+        assert np.array_equal(out[k], want, equal_nan=True), k
+    hbtest.assert_maps_close(out[None], hbtest.run_oracle(fr[None], "f32", s), f"maps {h}x{w} L{levels} S{split}")
+    run.close()
