@@ -266,8 +266,14 @@ def main():
                 "flops_per_pair": FLOPS_PER_PAIR, "exps_per_pair": EXPS_PER_PAIR}
     stage = {"log_haar_ms": ms[0] / max(launches[0], 1), "posterior_ms": ms[1] / max(launches[1], 1),
              "recompose_ms": ms[2] / max(launches[2], 1), "call_ms": ms[3] / max(launches[3], 1)}
-    hbm_bytes = B * H * W * (12 if a.dtype == "f32" else 6) + B * H * W * 16
-    stage["log_haar_plus_recompose_GBps"] = hbm_bytes / ((stage["log_haar_ms"] + stage["recompose_ms"]) * 1e-3) / 1e9
+    # K1 algorithmic bytes: frames read; detail part (8 B/px) and the
+    # double-float low-pass observation (24 B per low-pass pixel) written.
+    k1_bytes = B * H * W * ((12 if a.dtype == "f32" else 6) + 8) + B * LL * 24
+    stage["log_haar_GBps"] = k1_bytes / (stage["log_haar_ms"] * 1e-3) / 1e9
+    # With one grid split, the MFMA kernel and <= 2 levels the posterior kernel
+    # writes the maps itself and the recomposition kernel is not launched.
+    stage["recompose_fused"] = bool(info["grid_split"] == 1 and info["posterior_kernel"] == "mfma"
+                                    and a.levels <= 2)
 
     plan.close()
 

@@ -693,6 +693,7 @@ constexpr float kBoxSlack = 1.0e-3f;
 
 struct PixelRef {
     float m, ahb, aox;
+    float mup;  // wave-level upper bound of every logit of the split
 };
 
 // Best probe of super-tile T for observation r (recentred on T): updates the
@@ -764,7 +765,10 @@ __device__ __forceinline__ void probe_part(const float *__restrict__ T, const fl
 // probes the one with the highest bound, then only super-tiles whose bound
 // exceeds the lowest best probe of the wave: the result equals a full probe
 // scan (a super-tile bounded below a pixel's best probe cannot improve it).
-template <int PW, int LPP>
+// With EXACT the wave takes the exact maximum over all of the split's nodes
+// when some weight could exceed 2^kFarGap; the MFMA kernel instead does that
+// over the chunks it keeps (far_gap_max below).
+template <int PW, int LPP, bool EXACT>
 __device__ PixelRef pixel_reference(const PosteriorArgs &a, const WaveWork &w, const float ph[3],
                                     const float pl[3], int part, const float zlo[3], const float zhi[3]) {
     const int lane = threadIdx.x & 63;
@@ -828,8 +832,8 @@ __device__ PixelRef pixel_reference(const PosteriorArgs &a, const WaveWork &w, c
         }
     }
     combine();
-    PixelRef ref{mlo, ahb, aox};
-    if (__any(!(mup - mlo <= kFarGap))) {
+    PixelRef ref{mlo, ahb, aox, mup};
+    if (EXACT && __any(!(mup - mlo <= kFarGap))) {
         // Exact maximum over this split's nodes, difference form.
         float mx = mlo;
         for (int si = w.s0 + part; si < w.s1; si += LPP) {
@@ -886,6 +890,46 @@ __global__ __launch_bounds__(kBlockThreads) void k_reference(PosteriorArgs a) {
         if (si != best && box_bound(T + 8, r) > mlo) probe_supertile(T, r, mlo, ahb, aox);
     }
     a.gref[i] = mlo;
+}
+
+// Exact maximum logit over the nodes of the chunks a wave keeps (the same
+// super-tile and chunk tests as the main loop), difference form; each pixel's
+// LPP lanes split every chunk's nodes.  Returns max(current, that maximum).
+template <int PW, int LPP>
+__device__ float far_gap_max(const PosteriorArgs &a, const WaveWork &w, const float ph[3], const float pl[3],
+                             int part, const float zlo[3], const float zhi[3], float mmin, float cur) {
+    const int lane = threadIdx.x & 63;
+    const float nskip = -a.skip_log2;
+    float mx = cur;
+    for (int g = w.s0; g < w.s1; g += 64) {
+        float rbox[6];
+        const int sl = g + lane;
+        unsigned long long smask = __ballot(sl < w.s1 && wave_super_bound(a, sl, zlo, zhi, rbox) - mmin > nskip);
+        while (smask) {
+            const int si = g + __builtin_ctzll(smask);
+            smask &= smask - 1;
+            const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+            wave_super_bound(a, si, zlo, zhi, rbox);
+            float r[3];
+            recentre(T, ph, pl, r);
+            const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
+            for (int cg = 0; cg < a.chunks_per_super; cg += 64) {
+                const int ct = min(cg + lane, a.chunks_per_super - 1);
+                unsigned long long mask = __ballot(cg + lane < a.chunks_per_super &&
+                                                   box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > nskip);
+                while (mask) {
+                    const float *__restrict__ C = C0 + (size_t)(cg + __builtin_ctzll(mask)) * kChunkFloats;
+                    mask &= mask - 1;
+                    for (int j = part; j < kChunkNodes; j += LPP) {
+                        const float d0 = r[0] - C[j], d1 = r[1] - C[16 + j], d2 = r[2] - C[32 + j];
+                        mx = fmaxf(mx, -fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
+                    }
+                }
+            }
+        }
+    }
+    if (LPP == 2) mx = fmaxf(mx, __shfl_xor(mx, PW));
+    return mx;
 }
 
 // Fused recomposition for one split and n <= 2: every lane of pixel row lp
@@ -965,7 +1009,28 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(7
     }
     float zlo[3], zhi[3];
     wave_obs_box(ph, pl, zlo, zhi);
-    const PixelRef ref = pixel_reference<PW, LPP>(a, w, ph, pl, part, zlo, zhi);
+    PixelRef ref = pixel_reference<PW, LPP, false>(a, w, ph, pl, part, zlo, zhi);
+
+    // Skipping.  A chunk (or super-tile) whose logit upper bound lies more
+    // than skip_log2 below every pixel's reference has every weight below
+    // 2^-skip_log2 (exactly 0 in float32 at kExactSkipLog2, so then leaving
+    // it out changes no bit).  The bound is taken between the chunk's box and
+    // the box of the wave's observations (min reference over the wave), one
+    // chunk per lane.
+    const float nskip = -a.skip_log2;
+    float mmin = ref.m;
+    if (a.gref) {
+        long long p;
+        wave_pixel(a, w, lane % PW, p);
+        mmin = fmaxf(mmin, a.gref[(size_t)w.f * a.LL + p]);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mmin = fminf(mmin, __shfl_xor(mmin, o));
+    // If some weight could exceed 2^kFarGap relative to the best probe, take
+    // the exact maximum over the nodes of the chunks that will be kept (the
+    // only weights evaluated); a split far from the posterior usually keeps
+    // none, and then the reference needs no refinement.
+    if (__any(!(ref.mup - ref.m <= kFarGap))) ref.m = far_gap_max<PW, LPP>(a, w, ph, pl, part, zlo, zhi, mmin, ref.m);
 
     // B operand of block b: lane (lp, lk) holds coordinate lk of pixel b*16 + lp
     // (lk == 3: the homogeneous 1, and m for the constant term).
@@ -987,21 +1052,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(7
         R0[b] = R1[b] = R2[b] = 0.0f;
     }
 
-    // Skipping.  A chunk (or super-tile) whose logit upper bound lies more
-    // than skip_log2 below every pixel's reference has every weight below
-    // 2^-skip_log2 (exactly 0 in float32 at kExactSkipLog2, so then leaving
-    // it out changes no bit).  The bound is taken between the chunk's box and
-    // the box of the wave's observations (min reference over the wave), one
-    // chunk per lane.
-    const float nskip = -a.skip_log2;
-    float mmin = ref.m;
-    if (a.gref) {
-        long long p;
-        wave_pixel(a, w, lane % PW, p);
-        mmin = fmaxf(mmin, a.gref[(size_t)w.f * a.LL + p]);
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) mmin = fminf(mmin, __shfl_xor(mmin, o));
     const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
     unsigned executed = 0;   // chunks evaluated by this wave
     // Super-tiles are tested one per lane; the kept ones are walked in order.
@@ -1141,7 +1191,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
     for (int k = 0; k < 3; ++k) load_obs(zf, a.LL, p, k, a.scale, ph[k], pl[k]);
     float zlo[3], zhi[3];
     wave_obs_box(ph, pl, zlo, zhi);
-    const PixelRef ref = pixel_reference<PW, 1>(a, w, ph, pl, 0, zlo, zhi);
+    const PixelRef ref = pixel_reference<PW, 1, true>(a, w, ph, pl, 0, zlo, zhi);
     const float nm = -ref.m;
     float R0 = 0.f, R1 = 0.f, R2 = 0.f, K0 = 0.f, K1 = 0.f, K2 = 0.f;
     for (int si = w.s0; si < w.s1; ++si) {
