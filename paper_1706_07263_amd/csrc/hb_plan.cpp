@@ -108,12 +108,17 @@ Dims make_dims(const hb_plan_desc_t &d) {
 }
 
 int auto_split(const Dims &dm, int n_tiles, int max_batch) {
-    // Aim for about four waves per SIMD (1024 SIMDs) from a full batch.  The
-    // split is fixed per plan, so a frame gives the same bits in any batch.
+    // One split unless a full batch gives fewer than kMinWaves waves.  With
+    // skipping, a split adds a reference pass, a global-reference kernel and
+    // the merge kernel, and far splits still pay their per-wave set-up:
+    // measured per frame at batch 1, one split was fastest from 640x480
+    // (600 waves) to 3840x2160.  The split is fixed per plan, so a frame gives
+    // the same bits in any batch.
+    constexpr long long kMinWaves = 256;
     const long long per_wave = 16LL * kPixelBlocks;
     const long long waves = std::max(1LL, ((long long)max_batch * dm.LL + per_wave - 1) / per_wave);
     int s = 1;
-    while (s < 64 && waves * s < 4096) s *= 2;
+    while (s < 64 && waves * s < kMinWaves) s *= 2;
     return std::max(1, std::min(s, n_tiles));
 }
 
