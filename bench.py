@@ -96,8 +96,12 @@ def cpu_baseline(target_s: float, levels: int, grid: int, quiet: bool):
     dt = time.perf_counter() - t0
     rows = int(min(1080, max(b, rows * target_s / max(dt, 1e-3)))) // b * b
     rows = max(rows, b)
-    if rows == 1080 and dt * 1080 / (4 * b) < 0.5 * target_s:
-        n = int(min(8, max(1, round(target_s / (dt * 1080 / (4 * b))))))
+    t0 = time.perf_counter()
+    orc.estimate(hbtest.oracle_params(1920, rows, s), model, fr[:, :rows])
+    dt = time.perf_counter() - t0
+    if rows == 1080 and dt < 0.5 * target_s:
+        # a whole frame is quick: time frames 0 .. n-1 together instead
+        n = int(min(8, max(2, round(target_s / dt))))
         fr = synth.config3(tuple(range(n))).frames.astype(np.float64)
         t0 = time.perf_counter()
         orc.estimate(hbtest.oracle_params(1920, 1080, s), model, fr)
@@ -106,9 +110,6 @@ def cpu_baseline(target_s: float, levels: int, grid: int, quiet: bool):
         return {"value": n / dt, "unit": "frames/s", "cores": orc.threads(), "kind": "oracle",
                 "sample": f"frames 0..{n - 1} (1920x1080, {(1080 // b) * (1920 // b)} low-pass pixels x "
                           f"{grid * grid} nodes each), {dt:.2f} s"}
-    t0 = time.perf_counter()
-    orc.estimate(hbtest.oracle_params(1920, rows, s), model, fr[:, :rows])
-    dt = time.perf_counter() - t0
     frac = rows / 1080.0
     log(f"cpu oracle: {rows} rows x 1920 in {dt:.2f} s on {orc.threads()} threads", quiet)
     return {"value": frac / dt, "unit": "frames/s", "cores": orc.threads(), "kind": "oracle",
