@@ -34,8 +34,8 @@ EXPS_PER_PAIR = 1
 # profiles/hot_path_1080p_L2_G256_b8.md, valid for the device sources whose
 # combined sha256 (kernel_source_sha) starts with PROFILED_KERNEL_SHA; reported
 # as null for any other source or workload.
-PROFILED_KERNEL_SHA = "17dce68b16eafb7e"
-PROFILED_POSTERIOR_TRAFFIC = 146.99e6
+PROFILED_KERNEL_SHA = "a986f9e8f8a6739f"
+PROFILED_POSTERIOR_TRAFFIC = 706.99e6
 KERNEL_SOURCES = ("hb_kernels.hip", "hb_internal.h", "hb_df.h")
 
 
