@@ -1024,6 +1024,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(7
         wave_pixel(a, w, lane % PW, p);
         mmin = fmaxf(mmin, a.gref[(size_t)w.f * a.LL + p]);
     }
+    // A pixel without a finite logit (a NaN observation) gets NaN maps
+    // whatever is kept; it must not switch skipping off for its wave.
+    if (!(mmin > -INFINITY)) mmin = INFINITY;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mmin = fminf(mmin, __shfl_xor(mmin, o));
     // If some weight could exceed 2^kFarGap relative to the best probe, take

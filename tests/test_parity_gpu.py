@@ -410,3 +410,34 @@ def test_maps_are_estimate_plus_detail_part(torch_cuda, h, w, levels, split, off
         assert np.array_equal(out[k], want, equal_nan=True), k
     hbtest.assert_maps_close(out[None], hbtest.run_oracle(fr[None], "f32", s), f"maps {h}x{w} L{levels} S{split}")
     run.close()
+
+
+def test_nan_pixels_do_not_switch_skipping_off(torch_cuda):
+    """NaN observations give NaN blocks; they do not lower their wave's skip
+    reference, so the evaluated work and the other pixels' maps stay as
+    without them."""
+    from paper_1706_07263_amd import hb
+    fr, _, _ = synth.single_frame(128, 192, config=64)
+    bad = fr.copy()
+    rng = np.random.default_rng(3)
+    ys, xs = rng.integers(0, 128, 24), rng.integers(0, 192, 24)
+    bad[ys, xs, rng.integers(0, 3, 24)] = np.nan
+    s = _settings(levels=2, grid=256)
+    run = hbtest.GpuRun(192, 128, s, grid_split=1)
+    out, work = [], []
+    for x in (fr, bad):
+        hb.hb_plan_set_timing(run.plan.handle, True)
+        out.append(run(x[None]))
+        work.append(hb.hb_plan_get_work(run.plan.handle)[0])
+        hb.hb_plan_set_timing(run.plan.handle, False)
+    print("evaluated pairs without / with NaN pixels", work)
+    assert work[1] <= work[0] * 1.02
+    nanblk = np.zeros((128, 192), bool)
+    for y, x in zip(ys, xs):
+        nanblk[y // 4 * 4:y // 4 * 4 + 4, x // 4 * 4:x // 4 * 4 + 4] = True
+    assert np.all(np.isnan(out[1][0, :2][:, nanblk]))
+    # the same up to float32 rounding of sums whose kept sets differ by
+    # weights below 2^-45
+    assert np.max(np.abs(out[1][0, :2][:, ~nanblk] - out[0][0, :2][:, ~nanblk])) <= hbtest.TOL_HB
+    hbtest.assert_maps_close(out[1], hbtest.run_oracle(bad[None], "f32", s), "NaN pixels")
+    run.close()
