@@ -79,8 +79,11 @@ inline int super_floats(int side) {
 constexpr int kStripPixels = 2048;
 constexpr int kBlockThreads = 256;
 
-// Pixel blocks of 16 per wave in the posterior kernel.
-constexpr int kPixelBlocks = 2;
+// Pixel blocks of 16 per wave in the posterior kernel.  One block (an 8 x 2
+// tile of LL pixels) measured fastest: tighter skip boxes and shorter waves
+// (a shorter tail at the end of a launch) outweigh the per-pixel cost of
+// walking the kept super-tiles; two blocks were 1-11% slower.
+constexpr int kPixelBlocks = 1;
 
 // Partial moments per LL pixel and grid split:
 //   [0] logit reference, [1] S0, [2] S1 about the anchor, [3] S2 about the anchor,

@@ -795,10 +795,11 @@ __device__ PixelRef pixel_reference(const PosteriorArgs &a, const WaveWork &w, c
     }
     best = __builtin_amdgcn_readfirstlane(best);
     float mlo = -INFINITY, ahb = 0.0f, aox = 0.0f;
-    auto combine = [&]() {  // the LPP lanes of a pixel agree (lower half wins ties)
-        if (LPP == 2) {
-            const float om = __shfl_xor(mlo, PW), oh = __shfl_xor(ahb, PW), oo = __shfl_xor(aox, PW);
-            const bool take = part == 0 ? (om > mlo) : !(mlo > om);
+    auto combine = [&]() {  // the LPP lanes of a pixel agree (the lower part wins ties)
+#pragma unroll
+        for (int o = PW; o < 64; o <<= 1) {
+            const float om = __shfl_xor(mlo, o), oh = __shfl_xor(ahb, o), oo = __shfl_xor(aox, o);
+            const bool take = (lane & o) == 0 ? (om > mlo) : !(mlo > om);
             if (take) {
                 mlo = om;
                 ahb = oh;
@@ -847,7 +848,8 @@ __device__ PixelRef pixel_reference(const PosteriorArgs &a, const WaveWork &w, c
                     mx = fmaxf(mx, -fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
                 }
         }
-        if (LPP == 2) mx = fmaxf(mx, __shfl_xor(mx, PW));
+#pragma unroll
+        for (int o = PW; o < 64; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
         ref.m = mx;
     }
     return ref;
@@ -928,7 +930,8 @@ __device__ float far_gap_max(const PosteriorArgs &a, const WaveWork &w, const fl
             }
         }
     }
-    if (LPP == 2) mx = fmaxf(mx, __shfl_xor(mx, PW));
+#pragma unroll
+    for (int o = PW; o < 64; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
     return mx;
 }
 
@@ -986,10 +989,10 @@ __device__ __forceinline__ void fused_maps(const PosteriorArgs &a, const WaveWor
 // [r0^2, r1^2, r2^2, m] per super-tile.  Each lane then holds 1 pixel x the 4
 // nodes of one chunk row (lane l: pixel l % 16, THb row l / 16, SO2 offsets
 // 0..3) and runs the exponentials and the moments on the VALU.
-// Seven waves per SIMD (72 VGPRs; a few values spill outside the chunk loop)
-// measured fastest: 6 and 8 were slower on the 1080p workload.
+// Eight waves per SIMD (one 16-pixel block per wave, 60 VGPRs, no VGPR
+// spills) measured fastest on the 1080p workload.
 template <int PB>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_posterior(PosteriorArgs a) {
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_posterior(PosteriorArgs a) {
     constexpr int PW = 16 * PB;
     constexpr int LPP = 64 / PW;
     const int lane = threadIdx.x & 63;
