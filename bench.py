@@ -29,13 +29,13 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # offset), 1 add + 2 mul + 2 add (three moments) = 15 flops, plus one exp.
 FLOPS_PER_PAIR = 15
 EXPS_PER_PAIR = 1
-# HBM bytes per posterior launch of the default workload (8 frames), from the
+# HBM bytes per posterior launch of the default workload (16 frames), from the
 # rocprofv3 FETCH_SIZE/WRITE_SIZE runs summarised in
-# profiles/hot_path_1080p_L2_G256_b8.md, valid for the device sources whose
+# profiles/hot_path_1080p_L2_G256_b16.md, valid for the device sources whose
 # combined sha256 (kernel_source_sha) starts with PROFILED_KERNEL_SHA; reported
 # as null for any other source or workload.
-PROFILED_KERNEL_SHA = "a986f9e8f8a6739f"
-PROFILED_POSTERIOR_TRAFFIC = 706.99e6
+PROFILED_KERNEL_SHA = "dca35512a8019941"
+PROFILED_POSTERIOR_TRAFFIC = 1140.56e6
 KERNEL_SOURCES = ("hb_kernels.hip", "hb_internal.h", "hb_df.h")
 
 
@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--levels", type=int, default=2)
     ap.add_argument("--grid", type=int, default=256)
@@ -74,6 +74,21 @@ def parse():
 def log(msg, quiet=False):
     if not quiet:
         print(msg, file=sys.stderr, flush=True)
+
+
+def _render_frame(job):
+    from paper_1706_07263_amd import synth
+    i, dtype = job
+    return synth.config3((i,), dtype=dtype).frames
+
+
+def render_video(idx, dtype: str, workers: int = 8) -> np.ndarray:
+    """Frames idx of the 1920x1080 video, rendered in fresh worker processes."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    ctx = multiprocessing.get_context("spawn")
+    with ProcessPoolExecutor(max_workers=max(1, min(workers, len(idx))), mp_context=ctx) as pool:
+        return np.concatenate(list(pool.map(_render_frame, [(i, dtype) for i in idx])))
 
 
 def cpu_baseline(target_s: float, levels: int, grid: int, quiet: bool):
@@ -102,7 +117,7 @@ def cpu_baseline(target_s: float, levels: int, grid: int, quiet: bool):
     if rows == 1080 and dt < 0.5 * target_s:
         # a whole frame is quick: time frames 0 .. n-1 together instead
         n = int(min(8, max(2, round(target_s / dt))))
-        fr = synth.config3(tuple(range(n))).frames.astype(np.float64)
+        fr = render_video(list(range(n)), "f32").astype(np.float64)
         t0 = time.perf_counter()
         orc.estimate(hbtest.oracle_params(1920, 1080, s), model, fr)
         dt = time.perf_counter() - t0
@@ -215,7 +230,8 @@ def main():
     H, W = 1080, 1920
     log(f"generating {B} synthetic 1080p frames", a.quiet)
     idx = [int(i * 300 / B) for i in range(B)]
-    wl = synth.config3(idx, dtype=a.dtype)
+    wl = synth.config3((0,), dtype=a.dtype)
+    wl.frames = render_video(idx, a.dtype)
     settings = dict(wl.plan)
     settings["levels"], settings["grid_thb"], settings["grid_so2"] = a.levels, a.grid, a.grid
 
@@ -256,7 +272,7 @@ def main():
     eval_per_launch = evaluated / max(launches[1], 1) if evaluated else pairs_per_launch
     achieved = eval_per_launch * FLOPS_PER_PAIR / k2_s / 1e12
     sha = kernel_source_sha()
-    default_workload = (B, a.levels, a.grid, a.dtype, a.split) == (8, 2, 256, "f32", 0)
+    default_workload = (B, a.levels, a.grid, a.dtype, a.split) == (16, 2, 256, "f32", 0)
     traffic = PROFILED_POSTERIOR_TRAFFIC if (sha == PROFILED_KERNEL_SHA and default_workload) else None
     roofline = {"bound": "alu", "kernel": "k_posterior", "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
@@ -301,6 +317,19 @@ def main():
         half = {"frames_per_s": round(fps16, 3), "vs_fp32": round(fps16 / fps, 4)}
         log(f"fp16 storage: {fps16:.1f} frames/s", a.quiet)
         del frames16
+    # Throughput at the batch sizes of the video workload (the first b of the
+    # frames above, one plan per batch size).
+    sweep = {}
+    if not a.no_table1:
+        for b in (1, 4, 8, 16):
+            if b > B:
+                continue
+            d = hb.make_desc(W, H, levels=a.levels, dtype=a.dtype, max_batch=b, grid_thb=a.grid,
+                             grid_so2=a.grid, lam=settings["lam"], sigma=settings["sigma"])
+            sub = frames[:b]
+            subm = [m[:b] for m in maps]
+            sweep[str(b)] = round(time_plan(hb, torch, d, synth.spectra(), sub, subm, stream, a.steps, a.warmup), 2)
+        log(f"batch sweep (frames/s): {sweep}", a.quiet)
     del frames, maps
     torch.cuda.empty_cache()
     serve = serving(a) if a.serve_seconds > 0 else None
@@ -322,6 +351,7 @@ def main():
         "mpixel_per_s": round(fps * H * W / 1e6, 2),
         "stages_ms_per_call": {k: round(v, 4) for k, v in stage.items()},
         "roofline": roofline,
+        "batch_sweep_frames_per_s": sweep or None,
         "fp16_storage": half,
         "table1_analogue": table1,
         "cpu_baseline": cpu,

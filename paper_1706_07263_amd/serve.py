@@ -451,10 +451,12 @@ def workload_requests(duration_s: float, classes: Sequence[Tuple[int, int, int, 
 
 def render_sources(classes: Sequence[ShapeClass], n_sources: int = 1, workers: int = 4):
     """Pre-render frames per class (seeded), in parallel processes."""
+    import multiprocessing
     from concurrent.futures import ProcessPoolExecutor
-    from paper_1706_07263_amd import synth
     jobs = [(c.height, c.width, c.dtype, i) for c in classes for i in range(n_sources)]
-    with ProcessPoolExecutor(max_workers=max(1, min(workers, len(jobs)))) as pool:
+    # fresh interpreters: the caller may already hold a GPU context
+    ctx = multiprocessing.get_context("spawn")
+    with ProcessPoolExecutor(max_workers=max(1, min(workers, len(jobs))), mp_context=ctx) as pool:
         frames = list(pool.map(_render_one, jobs))
     out = {}
     for (c, i), fr in zip([(c, i) for c in classes for i in range(n_sources)], frames):
