@@ -67,6 +67,10 @@ __global__ void k_tikhonov_fp64(const double *__restrict__ in, double *__restric
     out[13] = ok ? 1.0 : 0.0;
 }
 
+// Clang vector types (the non-temporal builtins and the MFMA builtins take these).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------------------
 // Storage-type loads.
 // ---------------------------------------------------------------------------
@@ -376,15 +380,17 @@ __device__ __forceinline__ void load_run(const T *p, float *v) {
     }
 }
 
+// Detail-part rows are streamed out (non-temporal): they are read again
+// only by the posterior's epilogue or the recomposition kernel.
 template <int BW>
 __device__ __forceinline__ void store_row(float2 *p, const float2 *o) {
     if constexpr (BW == 4) {
-        reinterpret_cast<float4 *>(p)[0] = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
-        reinterpret_cast<float4 *>(p)[1] = make_float4(o[2].x, o[2].y, o[3].x, o[3].y);
+        __builtin_nontemporal_store(f32x4{o[0].x, o[0].y, o[1].x, o[1].y}, reinterpret_cast<f32x4 *>(p));
+        __builtin_nontemporal_store(f32x4{o[2].x, o[2].y, o[3].x, o[3].y}, reinterpret_cast<f32x4 *>(p) + 1);
     } else if constexpr (BW == 2) {
-        reinterpret_cast<float4 *>(p)[0] = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
+        __builtin_nontemporal_store(f32x4{o[0].x, o[0].y, o[1].x, o[1].y}, reinterpret_cast<f32x4 *>(p));
     } else {
-        p[0] = o[0];
+        __builtin_nontemporal_store(f32x2{o[0].x, o[0].y}, reinterpret_cast<f32x2 *>(p));
     }
 }
 
@@ -533,14 +539,15 @@ __device__ __forceinline__ void write_maps(float *mhb, float *mox, float *mth, f
         th[i] = hb[i] + ox[i];
         so[i] = (th[i] > thb_eps) ? ox[i] / th[i] : __builtin_nanf("");
     }
+    // streaming stores (non-temporal): the maps are not read again here
     auto put = [&](float *m, const float *v) {
         if (!m) return;
         if constexpr (V == 4) {
-            *reinterpret_cast<float4 *>(m + o) = make_float4(v[0], v[1], v[2], v[3]);
+            __builtin_nontemporal_store(f32x4{v[0], v[1], v[2], v[3]}, reinterpret_cast<f32x4 *>(m + o));
         } else if constexpr (V == 2) {
-            *reinterpret_cast<float2 *>(m + o) = make_float2(v[0], v[1]);
+            __builtin_nontemporal_store(f32x2{v[0], v[1]}, reinterpret_cast<f32x2 *>(m + o));
         } else {
-            m[o] = v[0];
+            __builtin_nontemporal_store(v[0], m + o);
         }
     };
     put(mhb, hb);
@@ -549,22 +556,23 @@ __device__ __forceinline__ void write_maps(float *mhb, float *mox, float *mth, f
     put(mso, so);
 }
 
-// V consecutive detail-part values from offset o.
+// V consecutive detail-part values from offset o (streaming loads).
 template <int V>
 __device__ __forceinline__ void load_detail(const float2 *det, size_t o, float2 *dp) {
     if constexpr (V == 4) {
-        const float4 x = *reinterpret_cast<const float4 *>(det + o);
-        const float4 y = *reinterpret_cast<const float4 *>(det + o + 2);
+        const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(det + o));
+        const f32x4 y = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(det + o + 2));
         dp[0] = make_float2(x.x, x.y);
         dp[1] = make_float2(x.z, x.w);
         dp[2] = make_float2(y.x, y.y);
         dp[3] = make_float2(y.z, y.w);
     } else if constexpr (V == 2) {
-        const float4 x = *reinterpret_cast<const float4 *>(det + o);
+        const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(det + o));
         dp[0] = make_float2(x.x, x.y);
         dp[1] = make_float2(x.z, x.w);
     } else {
-        dp[0] = det[o];
+        const f32x2 x = __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(det + o));
+        dp[0] = make_float2(x.x, x.y);
     }
 }
 
@@ -592,8 +600,6 @@ __device__ __forceinline__ void load_detail(const float2 *det, size_t o, float2 
 // difference form, for grids too coarse for the expanded logit's precision).
 // ---------------------------------------------------------------------------
 constexpr float kFarGap = 64.0f;
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
     const float y = x - c;
