@@ -441,3 +441,19 @@ def test_nan_pixels_do_not_switch_skipping_off(torch_cuda):
     assert np.max(np.abs(out[1][0, :2][:, ~nanblk] - out[0][0, :2][:, ~nanblk])) <= hbtest.TOL_HB
     hbtest.assert_maps_close(out[1], hbtest.run_oracle(bad[None], "f32", s), "NaN pixels")
     run.close()
+
+
+@pytest.mark.parametrize("gt,gs", [(4096, 3), (3, 4096), (1024, 1024), (1, 4096)])
+def test_maximum_grid_sizes(torch_cuda, gt, gs):
+    """Grids at the largest extent the plan accepts along an axis (4096
+    nodes), and a 1024 x 1024 grid, on a small frame the oracle finishes."""
+    fr, _, _ = synth.single_frame(16, 24, config=82)
+    s = _settings(levels=1, grid=32)
+    s["grid_thb"], s["grid_so2"] = gt, gs
+    run = hbtest.GpuRun(24, 16, s)
+    gpu = run(fr[None])
+    info = run.plan.info()
+    assert info["n_nodes"] == gt * gs
+    err = hbtest.assert_maps_close(gpu, hbtest.run_oracle(fr[None], "f32", s), f"grid {gt}x{gs}")
+    print(f"grid {gt}x{gs}", info["posterior_kernel"], err)
+    run.close()
