@@ -771,10 +771,9 @@ __device__ __forceinline__ void probe_part(const float *__restrict__ T, const fl
 // probes the one with the highest bound, then only super-tiles whose bound
 // exceeds the lowest best probe of the wave: the result equals a full probe
 // scan (a super-tile bounded below a pixel's best probe cannot improve it).
-// With EXACT the wave takes the exact maximum over all of the split's nodes
-// when some weight could exceed 2^kFarGap; the MFMA kernel instead does that
-// over the chunks it keeps (far_gap_max below).
-template <int PW, int LPP, bool EXACT>
+// The caller refines the reference with far_gap_max when some weight could
+// exceed 2^kFarGap relative to it.
+template <int PW, int LPP>
 __device__ PixelRef pixel_reference(const PosteriorArgs &a, const WaveWork &w, const float ph[3],
                                     const float pl[3], int part, const float zlo[3], const float zhi[3]) {
     const int lane = threadIdx.x & 63;
@@ -840,24 +839,6 @@ __device__ PixelRef pixel_reference(const PosteriorArgs &a, const WaveWork &w, c
     }
     combine();
     PixelRef ref{mlo, ahb, aox, mup};
-    if (EXACT && __any(!(mup - mlo <= kFarGap))) {
-        // Exact maximum over this split's nodes, difference form.
-        float mx = mlo;
-        for (int si = w.s0 + part; si < w.s1; si += LPP) {
-            const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
-            float r[3];
-            recentre(T, ph, pl, r);
-            const float *__restrict__ C = T + kSupHdr + kMaxProbes * kProbeFloats;
-            for (int c = 0; c < a.chunks_per_super; ++c, C += kChunkFloats)
-                for (int j = 0; j < kChunkNodes; ++j) {
-                    const float d0 = r[0] - C[j], d1 = r[1] - C[16 + j], d2 = r[2] - C[32 + j];
-                    mx = fmaxf(mx, -fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
-                }
-        }
-#pragma unroll
-        for (int o = PW; o < 64; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-        ref.m = mx;
-    }
     return ref;
 }
 
@@ -1018,7 +999,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8
     }
     float zlo[3], zhi[3];
     wave_obs_box(ph, pl, zlo, zhi);
-    PixelRef ref = pixel_reference<PW, LPP, false>(a, w, ph, pl, part, zlo, zhi);
+    PixelRef ref = pixel_reference<PW, LPP>(a, w, ph, pl, part, zlo, zhi);
 
     // Skipping.  A chunk (or super-tile) whose logit upper bound lies more
     // than skip_log2 below every pixel's reference has every weight below
@@ -1191,6 +1172,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8
 
 // Direct kernel: one LL pixel per lane, logits in the difference form
 // t - m = -(r - v_g)^2 - m on the VALU with wave-uniform (scalar) node loads.
+// Skipping, the global reference and the exact maximum over kept chunks are
+// as in the MFMA kernel.
 __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArgs a) {
     constexpr int PW = 64;
     const int lane = threadIdx.x & 63;
@@ -1203,32 +1186,57 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
     for (int k = 0; k < 3; ++k) load_obs(zf, a.LL, p, k, a.scale, ph[k], pl[k]);
     float zlo[3], zhi[3];
     wave_obs_box(ph, pl, zlo, zhi);
-    const PixelRef ref = pixel_reference<PW, 1, true>(a, w, ph, pl, 0, zlo, zhi);
+    PixelRef ref = pixel_reference<PW, 1>(a, w, ph, pl, 0, zlo, zhi);
+    const float nskip = -a.skip_log2;
+    float mmin = ref.m;
+    if (a.gref) mmin = fmaxf(mmin, a.gref[(size_t)w.f * a.LL + p]);
+    if (!(mmin > -INFINITY)) mmin = INFINITY;  // NaN observation: see the MFMA kernel
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mmin = fminf(mmin, __shfl_xor(mmin, o));
+    if (__any(!(ref.mup - ref.m <= kFarGap))) ref.m = far_gap_max<PW, 1>(a, w, ph, pl, 0, zlo, zhi, mmin, ref.m);
     const float nm = -ref.m;
     float R0 = 0.f, R1 = 0.f, R2 = 0.f, K0 = 0.f, K1 = 0.f, K2 = 0.f;
-    for (int si = w.s0; si < w.s1; ++si) {
-        const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
-        float r[3];
-        recentre(T, ph, pl, r);
-        float L0 = 0.f, L1 = 0.f, L2 = 0.f;
-        const float *__restrict__ C = T + kSupHdr + kMaxProbes * kProbeFloats;
-        for (int c = 0; c < a.chunks_per_super; ++c, C += kChunkFloats) {
+    unsigned executed = 0;
+    for (int g = w.s0; g < w.s1; g += 64) {
+        float rbox[6];
+        const int sl = g + lane;
+        unsigned long long smask = __ballot(sl < w.s1 && wave_super_bound(a, sl, zlo, zhi, rbox) - mmin > nskip);
+        while (smask) {
+            const int si = g + __builtin_ctzll(smask);
+            smask &= smask - 1;
+            const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+            wave_super_bound(a, si, zlo, zhi, rbox);
+            float r[3];
+            recentre(T, ph, pl, r);
+            float L0 = 0.f, L1 = 0.f, L2 = 0.f;
+            const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
+            for (int cg = 0; cg < a.chunks_per_super; cg += 64) {
+                const int ct = min(cg + lane, a.chunks_per_super - 1);
+                unsigned long long mask = __ballot(cg + lane < a.chunks_per_super &&
+                                                   box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > nskip);
+                while (mask) {
+                    const float *__restrict__ C = C0 + (size_t)(cg + __builtin_ctzll(mask)) * kChunkFloats;
+                    mask &= mask - 1;
+                    ++executed;
 #pragma unroll
-            for (int j = 0; j < kChunkNodes; ++j) {
-                const float d0 = r[0] - C[j], d1 = r[1] - C[16 + j], d2 = r[2] - C[32 + j];
-                float t = fmaf(-d0, d0, nm);
-                t = fmaf(-d1, d1, t);
-                t = fmaf(-d2, d2, t);
-                const float wt = __builtin_amdgcn_exp2f(t);
-                L0 += wt;
-                L1 = fmaf(wt, C[64 + j], L1);
-                L2 = fmaf(wt, C[80 + j], L2);
+                    for (int j = 0; j < kChunkNodes; ++j) {
+                        const float d0 = r[0] - C[j], d1 = r[1] - C[16 + j], d2 = r[2] - C[32 + j];
+                        float t = fmaf(-d0, d0, nm);
+                        t = fmaf(-d1, d1, t);
+                        t = fmaf(-d2, d2, t);
+                        const float wt = __builtin_amdgcn_exp2f(t);
+                        L0 += wt;
+                        L1 = fmaf(wt, C[64 + j], L1);
+                        L2 = fmaf(wt, C[80 + j], L2);
+                    }
+                }
             }
+            kahan_add(R0, K0, L0);
+            kahan_add(R1, K1, fmaf(T[6] - ref.ahb, L0, L1));
+            kahan_add(R2, K2, fmaf(T[7] - ref.aox, L0, L2));
         }
-        kahan_add(R0, K0, L0);
-        kahan_add(R1, K1, fmaf(T[6] - ref.ahb, L0, L1));
-        kahan_add(R2, K2, fmaf(T[7] - ref.aox, L0, L2));
     }
+    if (a.work && lane == 0) atomicAdd(a.work, (unsigned long long)executed * PW * kChunkNodes);
     if (valid) {
         float *out = a.part + ((size_t)w.f * a.split + w.split) * kPartFields * a.LL;
         out[p] = ref.m;

@@ -505,8 +505,8 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
     const double h_so2 = d.grid_so2 > 1 ? d.thb_max * (d.so2_max - d.so2_min) / (d.grid_so2 - 1) : 0.0;
     p->use_mfma = p->radius * p->radius * std::max(h_thb, h_so2) <= kMfmaPrecisionBudget;
     p->info.posterior_kernel = p->use_mfma ? 0 : 1;
-    // Only the MFMA kernel skips chunks; exact skipping has no error.
-    p->info.skip_bound = (p->use_mfma && p->skip_log2 < kExactSkipLog2)
+    // Exact skipping (T = kExactSkipLog2) has no error.
+    p->info.skip_bound = (p->skip_log2 < kExactSkipLog2)
                              ? 2.0 * (double)p->n_nodes * std::exp2(-(double)p->skip_log2) * d.thb_max
                              : 0.0;
     if (hipMemcpy(p->d_tiles, tiles.data(), sizeof(float) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
@@ -580,7 +580,7 @@ hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_fram
         pa.part = p->d_part;
         pa.work = ev ? p->d_work : nullptr;
         if (ev) p->full_pairs += (long long)n_frames * p->dims.LL * p->n_nodes;
-        if (p->use_mfma && p->d_gref) {
+        if (p->d_gref) {
             pa.gref = p->d_gref;
             if (launch_reference(pa, s) != hipSuccess) return HB_ERR_DEVICE;
         }

@@ -457,3 +457,25 @@ def test_maximum_grid_sizes(torch_cuda, gt, gs):
     err = hbtest.assert_maps_close(gpu, hbtest.run_oracle(fr[None], "f32", s), f"grid {gt}x{gs}")
     print(f"grid {gt}x{gs}", info["posterior_kernel"], err)
     run.close()
+
+
+def test_direct_kernel_skips_on_a_narrow_posterior(torch_cuda):
+    """sigma = 1e-3 on a 256 x 256 grid takes the direct kernel (the expanded
+    logit would round too coarsely).  Its posterior covers a small part of
+    the grid; the kernel skips with the same bounds as the MFMA kernel and
+    matches the oracle.  On this small frame the fields change quickly
+    across a wave's 8 x 8 pixel tile, so the kept fraction is about a third
+    (a model of the 1080p frames gives 3%)."""
+    from paper_1706_07263_amd import hb
+    fr, _, _ = synth.single_frame(128, 192, config=64)
+    s = _settings(levels=2, grid=256, sigma=1e-3)
+    run = hbtest.GpuRun(192, 128, s, grid_split=1)
+    assert run.plan.info()["posterior_kernel"] == "direct"
+    hb.hb_plan_set_timing(run.plan.handle, True)
+    gpu = run(fr[None])
+    evaluated, full = hb.hb_plan_get_work(run.plan.handle)
+    hb.hb_plan_set_timing(run.plan.handle, False)
+    print("direct kernel evaluated fraction", evaluated / full)
+    assert full == 32 * 48 * 256 * 256 and 0 < evaluated < 0.5 * full
+    hbtest.assert_maps_close(gpu, hbtest.run_oracle(fr[None], "f32", s), "direct sigma 1e-3")
+    run.close()
