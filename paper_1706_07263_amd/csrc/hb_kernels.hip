@@ -1,10 +1,16 @@
 // HIP kernels of the haemoglobin-estimation path for gfx950 (MI355X).
 //
-//   K0  k_tikhonov_fp64  plan time, FP64: E, (E'E + gamma I)^-1 E'      (Method, Eq. 5)
-//   K1  k_log_haar       log-attenuation, n-level 2D Haar, Tikhonov on the
-//                        directional coefficients; LDS-staged strips (Eq. 1-2, 5)
-//   K2  k_posterior      posterior mean over the THb x SO2 grid on the low-pass band
-//   K3  k_recompose      split merge, inverse Haar, THb/SO2 maps           (Eq. 4, Fig. 1)
+//   K0  k_tikhonov_fp64     plan time, FP64: E, (E'E + gamma I)^-1 E'   (Method, Eq. 5)
+//   K1  k_log_haar_reg<n>   log-attenuation, n-level 2D Haar, Tikhonov on the
+//                           directional coefficients and the inverse Haar of
+//                           that detail part, one block per thread (n <= 2)
+//       k_log_haar          the same in LDS-staged strips (any n)  (Eq. 1-2, 4, 5)
+//   K2a k_reference         best probe over the whole grid (split grids only)
+//   K2  k_posterior         posterior mean over the THb x SO2 grid on the
+//                           low-pass band (MFMA logits); with one split it
+//                           also writes the maps                   (Fig. 1)
+//       k_posterior_direct  the same with VALU logits (coarse grids, small sigma)
+//   K3  k_recompose         split merge plus detail part to the THb/SO2 maps
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -1025,8 +1031,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8
     // none, and then the reference needs no refinement.
     if (__any(!(ref.mup - ref.m <= kFarGap))) ref.m = far_gap_max<PW, LPP>(a, w, ph, pl, part, zlo, zhi, mmin, ref.m);
 
-    // B operand of block b: lane (lp, lk) holds coordinate lk of pixel b*16 + lp
-    // (lk == 3: the homogeneous 1, and m for the constant term).
+    // Pixel operand (the MFMA B operand) of block b: lane (lp, lk) holds
+    // coordinate lk of pixel b*16 + lp (lk == 3: the homogeneous 1, and m for
+    // the constant term).
     float ah[PB], al[PB], am[PB];
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
