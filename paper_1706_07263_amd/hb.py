@@ -235,9 +235,29 @@ class Plan:
     def estimate(self, frames, maps: Sequence, stream=None) -> None:
         """frames: device tensor [n][H][W][3] (float32/float16, or int16/uint16
         bit patterns for bfloat16); maps: four device float32 tensors
-        [n][H][W] or None."""
+        [n][H][W] or None.  Shapes, dtypes, devices and contiguity are checked
+        here, since the library receives bare pointers."""
         import torch
+        d = self.desc
+        want = {HB_F32: (torch.float32,), HB_F16: (torch.float16,),
+                HB_BF16: (torch.int16, torch.uint16, torch.bfloat16)}[d.frame_dtype]
+        if frames.dtype not in want:
+            raise HbError(HB_ERR_INVALID_ARG, f"frames dtype {frames.dtype}, plan expects {want}")
+        if frames.dim() != 4 or tuple(frames.shape[1:]) != (d.height, d.width, 3):
+            raise HbError(HB_ERR_SHAPE, f"frames shape {tuple(frames.shape)}, plan expects "
+                                        f"[n][{d.height}][{d.width}][3]")
+        if not frames.is_cuda or not frames.is_contiguous():
+            raise HbError(HB_ERR_INVALID_ARG, "frames must be a contiguous device tensor")
         n = frames.shape[0]
+        if len(maps) != 4:
+            raise HbError(HB_ERR_INVALID_ARG, "maps: four tensors or None (Hb, HbO2, THb, SO2)")
+        for m in maps:
+            if m is None:
+                continue
+            if (m.dtype != torch.float32 or not m.is_cuda or not m.is_contiguous()
+                    or m.numel() < n * d.height * d.width or m.device != frames.device):
+                raise HbError(HB_ERR_INVALID_ARG, "each map must be a contiguous float32 tensor on the frames' "
+                                                  f"device with at least {n}x{d.height}x{d.width} values")
         ptrs = [m.data_ptr() if m is not None else 0 for m in maps]
         if stream is None:
             stream = torch.cuda.current_stream(frames.device)

@@ -479,3 +479,32 @@ def test_direct_kernel_skips_on_a_narrow_posterior(torch_cuda):
     assert full == 32 * 48 * 256 * 256 and 0 < evaluated < 0.5 * full
     hbtest.assert_maps_close(gpu, hbtest.run_oracle(fr[None], "f32", s), "direct sigma 1e-3")
     run.close()
+
+
+def test_binding_rejects_mismatched_tensors(torch_cuda):
+    """The Python binding checks what the library cannot see behind bare
+    pointers: frame shape, dtype, device, contiguity and map sizes."""
+    torch = torch_cuda
+    from paper_1706_07263_amd import hb
+    d = hb.make_desc(64, 32, levels=1, max_batch=2, grid_thb=16, grid_so2=16)
+    with hb.Plan(d, 0) as p:
+        p.set_forward_model(synth.spectra())
+        ok = torch.rand((2, 32, 64, 3), device="cuda") * 0.5 + 0.3
+        maps = [torch.empty((2, 32, 64), device="cuda") for _ in range(4)]
+        p.estimate(ok, maps)
+        torch.cuda.synchronize()
+        bad = [
+            (torch.rand((2, 64, 32, 3), device="cuda"), maps, hb.HB_ERR_SHAPE),
+            (ok.half(), maps, hb.HB_ERR_INVALID_ARG),
+            (ok.cpu(), maps, hb.HB_ERR_INVALID_ARG),
+            (ok.transpose(1, 2).contiguous().transpose(1, 2), maps, hb.HB_ERR_INVALID_ARG),
+            (ok, maps[:3], hb.HB_ERR_INVALID_ARG),
+            (ok, [maps[0][:1]] + maps[1:], hb.HB_ERR_INVALID_ARG),
+            (ok, [maps[0].double()] + maps[1:], hb.HB_ERR_INVALID_ARG),
+        ]
+        for fr, mp, status in bad:
+            with pytest.raises(hb.HbError) as e:
+                p.estimate(fr, mp)
+            assert e.value.status == status
+        p.estimate(ok, [None, maps[1], None, None])
+        torch.cuda.synchronize()
