@@ -136,6 +136,50 @@ def cpu_baseline(target_s: float, levels: int, grid: int, quiet: bool):
 PAPER_TABLE1_HZ = {"bayes_full_resolution": 3.54, "proposed_w1": 12.7, "proposed_w3": 14.4, "tikhonov": 43.5}
 
 
+def host_serial(torch, plan, host, dev, maps, stream, steps, warmup) -> float:
+    """Calls per second: copy the batch from pinned memory, then estimate,
+    one after the other on one stream."""
+    def step():
+        dev.copy_(host, non_blocking=True)
+        plan.estimate(dev, maps, stream)
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            step()
+    torch.cuda.synchronize()
+    return steps / (time.perf_counter() - t0)
+
+
+def host_overlapped(torch, plan, host, dev, maps, stream, steps, warmup) -> float:
+    """Calls per second with two device slots: a copy stream (default
+    priority) fills one slot while the compute stream estimates the other."""
+    slots = [dev, torch.empty_like(dev)]
+    copy_s = torch.cuda.Stream(dev.device)
+    copied = [torch.cuda.Event(), torch.cuda.Event()]
+    done = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def run(n):
+        for i in range(n):
+            k = i & 1
+            copy_s.wait_event(done[k])
+            with torch.cuda.stream(copy_s):
+                slots[k].copy_(host, non_blocking=True)
+            copied[k].record(copy_s)
+            stream.wait_event(copied[k])
+            plan.estimate(slots[k], maps, stream)
+            done[k].record(stream)
+    run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    return steps / (time.perf_counter() - t0)
+
+
 def time_plan(hb, torch, desc, spectra, frames, maps, stream, steps, warmup):
     with hb.Plan(desc, 0) as plan:
         plan.set_forward_model(spectra)
@@ -317,6 +361,27 @@ def main():
         half = {"frames_per_s": round(fps16, 3), "vs_fp32": round(fps16 / fps, 4)}
         log(f"fp16 storage: {fps16:.1f} frames/s", a.quiet)
         del frames16
+    # End to end with the frames copied from pinned host memory every step
+    # (the library takes device pointers, so this is context, not the value):
+    # serially on one stream, and overlapped (a copy stream fills one of two
+    # device slots while the other is estimated), for FP32 and FP16 storage.
+    pcie = None
+    if not a.no_table1 and a.dtype == "f32":
+        pcie = {"host_bytes_per_frame_f32": H * W * 12, "host_bytes_per_frame_f16": H * W * 6}
+        for tag, dev_frames, dt in (("f32", frames, "f32"), ("f16", frames.half(), "f16")):
+            host = dev_frames.cpu().pin_memory()
+            d_h = hb.make_desc(W, H, levels=a.levels, dtype=dt, max_batch=B, grid_thb=a.grid, grid_so2=a.grid,
+                               lam=settings["lam"], sigma=settings["sigma"], grid_split=a.split)
+            with hb.Plan(d_h, 0) as plan_h:
+                plan_h.set_forward_model(synth.spectra())
+                if tag == "f32":
+                    pcie["serial_frames_per_s_f32"] = round(
+                        host_serial(torch, plan_h, host, dev_frames, maps, stream, a.steps, a.warmup) * B, 2)
+                pcie[f"overlapped_frames_per_s_{tag}"] = round(
+                    host_overlapped(torch, plan_h, host, dev_frames, maps, stream, a.steps, a.warmup) * B, 2)
+            del host
+        log(f"frames from pinned host memory (frames/s): {pcie}", a.quiet)
+
     # Throughput at the batch sizes of the video workload (the first b of the
     # frames above, one plan per batch size).
     sweep = {}
@@ -352,6 +417,7 @@ def main():
         "stages_ms_per_call": {k: round(v, 4) for k, v in stage.items()},
         "roofline": roofline,
         "batch_sweep_frames_per_s": sweep or None,
+        "pinned_host_input": pcie,
         "fp16_storage": half,
         "table1_analogue": table1,
         "cpu_baseline": cpu,
