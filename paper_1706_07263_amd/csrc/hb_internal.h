@@ -28,9 +28,10 @@ namespace hb {
 //     [64 + j]: Hb of node j minus header[6]     [80 + j]: HbO2 minus header[7]
 //     [96..98] chunk box lower corner, [99..101] upper corner (relative)
 //     [104 + 4 a + (0..3)], a = 0..3: for the chunk row of THb offset a,
-//       Hb = A_h + B_h s and HbO2 = A_o + B_o s at SO2 offset s = 0..3
-//       (exact on a product grid: THb is constant along the row and SO2 is
-//       linear in s), as (A_h, B_h, A_o, B_o) relative to header[6], [7].
+//       Hb = A_h + B_h s at SO2 offset s = 0..3 relative to header[6] (exact
+//       on a product grid: THb is constant along the row and SO2 is linear
+//       in s), and the row's THb minus header[6] + header[7], as
+//       (A_h, B_h, A_t, 0); HbO2 = THb - Hb.
 // The first 64 floats of a chunk are exactly the A operand of a 16x16x4 MFMA
 // (lane l reads float l: node row i = l % 16, column k = l / 16); the B
 // operand carries twice the pixel's relative coordinates, so lane l of the

@@ -1103,8 +1103,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8
                 return got;
             };
             // Weights of the row's four nodes (SO2 offsets s = 0..3): their sum
-            // W0 and first moment W1 = sum s w_s give the row's Hb and HbO2
-            // moments through the affine row coefficients.
+            // W0 and first moment W1 = sum s w_s give the row's Hb moment
+            // through the affine row coefficients, and W0 its THb moment (THb
+            // is constant along the row); HbO2 = THb - Hb after the super-tile.
             auto eval = [&](float bv, const float4 &qm) {
                 ++executed;
 #pragma unroll
@@ -1116,7 +1117,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8
                     const float W1 = fmaf(3.0f, w3, fmaf(2.0f, w2, w1));
                     L0[b] += W0;
                     L1[b] = fmaf(qm.x, W0, fmaf(qm.y, W1, L1[b]));
-                    L2[b] = fmaf(qm.z, W0, fmaf(qm.w, W1, L2[b]));
+                    L2[b] = fmaf(qm.z, W0, L2[b]);
                 }
             };
             float bA, bB;
@@ -1136,7 +1137,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8
         for (int b = 0; b < PB; ++b) {
             R0[b] += L0[b];
             R1[b] += fmaf(chb - anc_hb[b], L0[b], L1[b]);
-            R2[b] += fmaf(cox - anc_ox[b], L0[b], L2[b]);
+            R2[b] += fmaf(cox - anc_ox[b], L0[b], L2[b] - L1[b]);   // HbO2 = THb - Hb
         }
       }
     }

@@ -277,8 +277,10 @@ double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const doubl
                         const double so2 = lin(d.so2_min, d.so2_max, GS, b0 + 4 * cs);
                         Q[0] = (float)(thb * (1.0 - so2) - (double)chb_c);
                         Q[1] = (float)(-thb * dso2);
-                        Q[2] = (float)(thb * so2 - (double)cox_c);
-                        Q[3] = (float)(thb * dso2);
+                        // THb is constant along the row: the HbO2 moment is the
+                        // THb moment minus the Hb moment
+                        Q[2] = (float)(thb - (double)chb_c - (double)cox_c);
+                        Q[3] = 0.0f;
                     }
                     for (int k = 102; k < 104; ++k) C[k] = 0.0f;
                 }
