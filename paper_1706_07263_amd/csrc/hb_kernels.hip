@@ -700,7 +700,7 @@ __device__ __forceinline__ float box_box_bound(const float *box, const float r[6
     return -fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
 }
 
-// Widening of the observation box for the rounding of high + low parts.
+// Widening of the wave's observation box for rounding (scaled units).
 constexpr float kBoxSlack = 1.0e-3f;
 
 struct PixelRef {
@@ -726,7 +726,9 @@ __device__ __forceinline__ void probe_supertile(const float *__restrict__ T, con
 }
 
 // Observation box of the wave (every lane's pixel), for bounds that hold for
-// all of its pixels at once.
+// all of its pixels at once; widened by kBoxSlack once here, which covers the
+// rounding of high + low parts, of the super-tile centre and of the
+// recentring subtractions below.
 __device__ __forceinline__ void wave_obs_box(const float ph[3], const float pl[3], float zlo[3], float zhi[3]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) zlo[k] = zhi[k] = ph[k] + pl[k];
@@ -737,18 +739,24 @@ __device__ __forceinline__ void wave_obs_box(const float ph[3], const float pl[3
             zlo[k] = fminf(zlo[k], __shfl_xor(zlo[k], o));
             zhi[k] = fmaxf(zhi[k], __shfl_xor(zhi[k], o));
         }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        zlo[k] -= kBoxSlack;
+        zhi[k] += kBoxSlack;
+    }
 }
 
-// Upper bound of the logit between the wave's observation box and the node
-// box of super-tile si (widened for the rounding of high + low parts).
+// Upper bound of the logit between the wave's (widened) observation box and
+// the node box of super-tile si; rbox is the observation box relative to the
+// super-tile's centre.
 __device__ __forceinline__ float wave_super_bound(const PosteriorArgs &a, int si, const float zlo[3],
                                                   const float zhi[3], float rbox[6]) {
     const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const float c = T[k] + T[3 + k];
-        rbox[k] = (zlo[k] - c) - kBoxSlack;
-        rbox[3 + k] = (zhi[k] - c) + kBoxSlack;
+        rbox[k] = zlo[k] - c;
+        rbox[3 + k] = zhi[k] - c;
     }
     return box_box_bound(T + 8, rbox);
 }
