@@ -32,10 +32,27 @@ namespace hb {
 //       on a product grid: THb is constant along the row and SO2 is linear
 //       in s), and the row's THb minus header[6] + header[7], as
 //       (A_h, B_h, A_t, 0); HbO2 = THb - Hb.
-// The first 64 floats of a chunk are exactly the A operand of a 16x16x4 MFMA
-// (lane l reads float l: node row i = l % 16, column k = l / 16); the B
-// operand carries twice the pixel's relative coordinates, so lane l of the
-// result holds pixel l % 16 and the four nodes of chunk row l / 16.
+// The first 64 floats of a chunk hold the node coordinates and squared
+// norms (lane l: node row i = l % 16, column k = l / 16).
+//
+// Split operand table (the A operand of the posterior's 16x16x32 bf16 MFMA),
+// kSplitLaneBytes per lane and kSplitChunkBytes per chunk, chunks in the
+// order of the super-tile table: lane l = 16 g + i holds 8 bf16 values for
+// node i of the chunk.  Every FP32 value x used below is split exactly into
+// three bf16 parts x = x1 + x2 + x3 (each the nearest bf16 to what remains).
+// For g = 0..2 and coordinate v = node coordinate g the 8 values are
+//   (v1, v2, v1, v3, v2, v1, v3, v2)
+// and the pixel (B) operand carries the parts of u = twice the pixel's
+// coordinate g as (u1, u1, u2, u1, u2, u3, u2, u3), so the eight products
+// are every u_a v_b except u3 v3 (below 2^-34 |u v|).  For g = 3 the node
+// holds the parts of its squared-norm entry and three ones,
+// (n1, n2, n3, 1, 1, 1, 0, 0), and the pixel (1, 1, 1, c1, c2, c3, 0, 0)
+// with its constant c = -(|r|^2 + m).  The MFMA then forms the same
+// expanded logit as FP32 products of the FP32 values, up to its accumulation
+// rounding, and lane l of the result holds pixel l % 16 and the four nodes
+// of chunk row l / 16.
+constexpr int kSplitLaneBytes = 16;
+constexpr int kSplitChunkBytes = 64 * kSplitLaneBytes;
 // Precision rule for the MFMA kernel.  Its expanded logit rounds at the scale
 // of the squared super-tile radius R^2 (scaled units), and a coarse grid
 // (node spacing h in uM of Hb/HbO2) turns a logit error into an estimate error
@@ -80,11 +97,12 @@ inline int super_floats(int side) {
 constexpr int kStripPixels = 2048;
 constexpr int kBlockThreads = 256;
 
-// Pixel blocks of 16 per wave in the posterior kernel.  One block (an 8 x 2
-// tile of LL pixels) measured fastest: tighter skip boxes and shorter waves
-// (a shorter tail at the end of a launch) outweigh the per-pixel cost of
-// walking the kept super-tiles; two blocks were 1-11% slower.
-constexpr int kPixelBlocks = 1;
+// Pixel blocks of 16 per wave in the posterior kernel (an 8 x 4 tile of LL
+// pixels for two).  Each chunk's 1 KB split operand is loaded once per wave
+// and used for every block, so more blocks cut the vector-memory traffic per
+// pair; fewer blocks give tighter skip boxes (fewer pairs evaluated).  Two
+// measured fastest (one was 10% slower, bound by operand loads).
+constexpr int kPixelBlocks = 2;
 
 // Partial moments per LL pixel and grid split:
 //   [0] logit reference, [1] S0, [2] S1 about the anchor, [3] S2 about the anchor,
@@ -118,6 +136,7 @@ struct PosteriorArgs {
     int n_frames;
     const float *z;          // [n][6][LL]
     const float *supers;     // [n_supers][super_floats(side)]
+    const void *split_ops;   // [n_supers][chunks_per_super][kSplitChunkBytes] bf16 A operands
     int n_supers;
     int super_stride;        // floats
     int chunks_per_super;

@@ -75,7 +75,12 @@ __global__ void k_tikhonov_fp64(const double *__restrict__ in, double *__restric
 
 // Clang vector types (the non-temporal builtins and the MFMA builtins take these).
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x3 __attribute__((ext_vector_type(3)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+// Word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format).
+constexpr int kBufferWord3 = 0x00020000;
 
 // ---------------------------------------------------------------------------
 // Storage-type loads.
@@ -629,8 +634,32 @@ __device__ __forceinline__ float lane_sum_rows(float x) {
     return x + e;
 }
 
-__device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+__device__ __forceinline__ f32x4 mfma_16x16x32_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Pixel (B) operand of the split bf16 MFMA.  Lane groups 0..2 carry the
+// exact three-part split of u (twice the pixel's coordinate) in the order
+// that pairs with the node parts of the split operand table; group 3 carries
+// ones that pick up the node's squared-norm parts and the three parts of the
+// pixel's constant c = -(|r|^2 + m), paired with node ones.
+__device__ __forceinline__ bf16x8 split_pixel_operand(float u, float c, bool coord) {
+    const float x = coord ? u : c;
+    const __bf16 x1 = (__bf16)x;
+    const float r1 = x - (float)x1;
+    const __bf16 x2 = (__bf16)r1;
+    const __bf16 x3 = (__bf16)(r1 - (float)x2);
+    const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
+    bf16x8 b;
+    b[0] = coord ? x1 : one;
+    b[1] = coord ? x1 : one;
+    b[2] = coord ? x2 : one;
+    b[3] = x1;
+    b[4] = x2;
+    b[5] = x3;
+    b[6] = coord ? x2 : zero;
+    b[7] = coord ? x3 : zero;
+    return b;
 }
 
 // A wave takes a compact 8-wide tile of LL pixels (PW / 8 rows), four waves
@@ -982,18 +1011,20 @@ __device__ __forceinline__ void fused_maps(const PosteriorArgs &a, const WaveWor
     }
 }
 
-// MFMA kernel: a wave takes PB blocks of 16 LL pixels.  Per super-tile and
-// 16-node chunk one v_mfma_f32_16x16x4_f32 forms the 16 x 16 logits
-//   t - m = [v_g, -|v_g|^2] . [2 r, 1] + (-(|r|^2 + m))
-// (nodes as rows, pixels as columns), whose per-pixel constant (the
-// accumulator input) comes from one more MFMA of -1 against
-// [r0^2, r1^2, r2^2, m] per super-tile.  Each lane then holds 1 pixel x the 4
-// nodes of one chunk row (lane l: pixel l % 16, THb row l / 16, SO2 offsets
-// 0..3) and runs the exponentials and the moments on the VALU.
-// Eight waves per SIMD (one 16-pixel block per wave, 60 VGPRs, no VGPR
-// spills) measured fastest on the 1080p workload.
+// MFMA kernel: a wave takes PB blocks of 16 LL pixels.  Per super-tile,
+// 16-node chunk and pixel block one v_mfma_f32_16x16x32_bf16 forms the
+// 16 x 16 logits
+//   t - m = [v_g, -|v_g|^2, 1] . [2 r, 1, -(|r|^2 + m)]
+// (nodes as rows, pixels as columns) from exact three-part bf16 splits of the
+// FP32 operands: every product except the smallest (u3 v3), in half the
+// cycles of the FP32 16x16x4 MFMA.  The node operand (1 KB per chunk) is
+// loaded once for all PB blocks.  Each lane then holds 1 pixel x the 4 nodes
+// of one chunk row (lane l: pixel l % 16, THb row l / 16, SO2 offsets 0..3)
+// and runs the exponentials and the moments on the VALU.
+// Two pixel blocks per wave (an 8 x 4 tile) at six waves per SIMD (78 VGPRs,
+// no spills) measured fastest on the 1080p workload.
 template <int PB>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_posterior(PosteriorArgs a) {
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_posterior(PosteriorArgs a) {
     constexpr int PW = 16 * PB;
     constexpr int LPP = 64 / PW;
     const int lane = threadIdx.x & 63;
@@ -1062,6 +1093,12 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8
 
     const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
     unsigned executed = 0;   // chunks evaluated by this wave
+    // Split operands through a buffer resource: the lane offset stays in a
+    // register and the chunk offset is scalar; loads past the table return 0.
+    const __amdgpu_buffer_rsrc_t split_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(a.split_ops), (short)0, a.n_supers * a.chunks_per_super * kSplitChunkBytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t super_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float *>(a.supers), (short)0, a.n_supers * a.super_stride * 4, kBufferWord3);
     // Super-tiles are tested one per lane; the kept ones are walked in order.
     for (int g = w.s0; g < w.s1; g += 64) {
       float rbox[6];
@@ -1074,19 +1111,23 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8
         wave_super_bound(a, si, zlo, zhi, rbox);
         const int kk = lk < 3 ? lk : 0;
         const float ch = T[kk], cl = T[3 + kk];
-        float av[PB];
-        f32x4 cv[PB];
+        bf16x8 av[PB];
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
             const float r = (ah[b] - ch) + (al[b] - cl);
-            av[b] = lk < 3 ? 2.0f * r : 1.0f;
-            const float a2 = lk < 3 ? r * r : am[b];
-            cv[b] = mfma_16x16x4(-1.0f, a2, zero4);   // -(|r|^2 + m) per pixel column
+            // |r|^2 + m over the pixel's four lanes (same value on each)
+            float a2 = lk < 3 ? r * r : am[b];
+            a2 += __shfl_xor(a2, 16);
+            a2 += __shfl_xor(a2, 32);
+            av[b] = split_pixel_operand(2.0f * r, -a2, lk < 3);
         }
         float L0[PB], L1[PB], L2[PB];
 #pragma unroll
         for (int b = 0; b < PB; ++b) L0[b] = L1[b] = L2[b] = 0.0f;
         const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
+        const int s_first = si * a.chunks_per_super;   // first chunk of the super-tile in the split table
+        // byte offset of the first chunk's row coefficients in the super-tile table
+        const int c_first = (si * a.super_stride + kSupHdr + kMaxProbes * kProbeFloats + 104) * 4;
         for (int cg = 0; cg < a.chunks_per_super; cg += 64) {
             const int ct = min(cg + lane, a.chunks_per_super - 1);
             const bool keep = cg + lane < a.chunks_per_super &&
@@ -1099,13 +1140,15 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8
             // loaded again), so the wait counts match on every path and a
             // wait for the current chunk never waits for the next one.
             int last = cg;
-            auto take = [&](float &bv, float4 &qm) -> bool {
+            auto take = [&](bf16x8 &bv, f32x3 &qm) -> bool {
                 const bool got = mask != 0;
                 last = got ? cg + __builtin_ctzll(mask | (1ull << 63)) : last;
                 mask &= mask - 1;
-                const float *__restrict__ C = C0 + (size_t)last * kChunkFloats;
-                bv = C[lane];
-                qm = *reinterpret_cast<const float4 *>(C + 104 + 4 * lk);
+                bv = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
+                                                    split_rsrc, lane * kSplitLaneBytes,
+                                                    (s_first + last) * kSplitChunkBytes, 0));
+                qm = __builtin_bit_cast(f32x3, __builtin_amdgcn_raw_buffer_load_b96(
+                                                   super_rsrc, lk * 16, c_first + last * (kChunkFloats * 4), 0));
                 // keep these loads ahead of the evaluation that follows
                 __builtin_amdgcn_sched_barrier(0);
                 return got;
@@ -1114,11 +1157,11 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8
             // W0 and first moment W1 = sum s w_s give the row's Hb moment
             // through the affine row coefficients, and W0 its THb moment (THb
             // is constant along the row); HbO2 = THb - Hb after the super-tile.
-            auto eval = [&](float bv, const float4 &qm) {
+            auto eval = [&](const bf16x8 &bv, const f32x3 &qm) {
                 ++executed;
 #pragma unroll
                 for (int b = 0; b < PB; ++b) {
-                    const f32x4 d = mfma_16x16x4(bv, av[b], cv[b]);
+                    const f32x4 d = mfma_16x16x32_bf16(bv, av[b], zero4);
                     const float w0 = __builtin_amdgcn_exp2f(d[0]), w1 = __builtin_amdgcn_exp2f(d[1]);
                     const float w2 = __builtin_amdgcn_exp2f(d[2]), w3 = __builtin_amdgcn_exp2f(d[3]);
                     const float W0 = (w0 + w1) + (w2 + w3);
@@ -1128,8 +1171,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(8
                     L2[b] = fmaf(qm.z, W0, L2[b]);
                 }
             };
-            float bA, bB;
-            float4 qA, qB;
+            bf16x8 bA, bB;
+            f32x3 qA, qB;
             take(bA, qA);
             while (true) {
                 const bool gotB = take(bB, qB);

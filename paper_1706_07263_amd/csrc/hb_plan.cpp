@@ -39,6 +39,7 @@ struct hb_plan_s {
     size_t k0_in = 0;         // doubles of K0 input
     float *d_mf = nullptr;    // FP32 M (6) + low-pass Tikhonov offset (2)
     float *d_tiles = nullptr;   // super-tile table
+    void *d_split = nullptr;    // split bf16 A operands of the chunks
     float *d_z = nullptr;
     float2 *d_det = nullptr;
     float *d_part = nullptr;
@@ -136,6 +137,7 @@ void free_plan(hb_plan_s *p) {
     (void)hipFree(p->d_k0);
     (void)hipFree(p->d_mf);
     (void)hipFree(p->d_tiles);
+    (void)hipFree(p->d_split);
     (void)hipFree(p->d_z);
     (void)hipFree(p->d_det);
     (void)hipFree(p->d_part);
@@ -321,6 +323,59 @@ double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const doubl
     return *std::max_element(radius.begin(), radius.end());
 }
 
+// Nearest bf16 (ties to even) of a finite float, and its float value.
+uint16_t bf16_nearest(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, sizeof(u));
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float x;
+    std::memcpy(&x, &u, sizeof(x));
+    return x;
+}
+// x = x1 + x2 + x3 exactly: each remainder is exact in float and the last one
+// has at most 8 significant bits.
+void split3(float x, uint16_t p[3]) {
+    p[0] = bf16_nearest(x);
+    const float r1 = x - bf16_value(p[0]);
+    p[1] = bf16_nearest(r1);
+    const float r2 = r1 - bf16_value(p[1]);
+    p[2] = bf16_nearest(r2);
+}
+
+// Split bf16 A operands of every chunk from the FP32 coordinates and
+// squared-norm entries of the super-tile table (layout in hb_internal.h).
+void build_split_ops(const std::vector<float> &table, int n_sup, int side, std::vector<uint16_t> &ops) {
+    const int stride = super_floats(side);
+    const int n_chunks = (side / 4) * (side / 4);
+    constexpr int kLaneHalves = kSplitLaneBytes / 2;
+    ops.assign((size_t)n_sup * n_chunks * 64 * kLaneHalves, 0);
+    for (int si = 0; si < n_sup; ++si)
+        for (int c = 0; c < n_chunks; ++c) {
+            const float *C = &table[(size_t)si * stride + kSupHdr + kMaxProbes * kProbeFloats + (size_t)c * kChunkFloats];
+            uint16_t *O = &ops[((size_t)si * n_chunks + c) * 64 * kLaneHalves];
+            for (int g = 0; g < 4; ++g)
+                for (int i = 0; i < 16; ++i) {
+                    uint16_t *L = O + (size_t)(16 * g + i) * kLaneHalves;
+                    uint16_t v[3];
+                    split3(C[16 * g + i], v);   // g = 3: the squared-norm entry
+                    if (g < 3) {
+                        const int order[8] = {0, 1, 0, 2, 1, 0, 2, 1};
+                        for (int e = 0; e < 8; ++e) L[e] = v[order[e]];
+                    } else {
+                        const uint16_t one = bf16_nearest(1.0f);
+                        for (int e = 0; e < 3; ++e) {
+                            L[e] = v[e];
+                            L[3 + e] = one;   // picks up the pixel's constant
+                        }
+                    }
+                }
+        }
+}
+
 }  // namespace
 
 extern "C" {
@@ -396,6 +451,8 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     st = HB_OK;
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_mf, sizeof(float) * 8);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_tiles, sizeof(float) * (size_t)p->n_tiles * super_floats(p->side));
+    if (st == HB_OK)
+        st = dev_alloc(p, &p->d_split, (size_t)kSplitChunkBytes * p->n_tiles * (p->side / 4) * (p->side / 4));
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_z, sizeof(float) * nb * 6 * LL);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_det, sizeof(float2) * nb * HW);
     if (st == HB_OK && desc->lowpass == HB_LOWPASS_BAYES)
@@ -513,6 +570,11 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
                              : 0.0;
     if (hipMemcpy(p->d_tiles, tiles.data(), sizeof(float) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
         return HB_ERR_DEVICE;
+    std::vector<uint16_t> split_ops;
+    build_split_ops(tiles, p->n_tiles, p->side, split_ops);
+    if (hipMemcpy(p->d_split, split_ops.data(), sizeof(uint16_t) * split_ops.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return HB_ERR_DEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return HB_ERR_DEVICE;
 
     for (int i = 0; i < 6; ++i) {
@@ -573,6 +635,7 @@ hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_fram
         pa.n_frames = n_frames;
         pa.z = p->d_z;
         pa.supers = p->d_tiles;
+        pa.split_ops = p->d_split;
         pa.n_supers = p->n_tiles;
         pa.super_stride = super_floats(p->side);
         pa.chunks_per_super = (p->side / 4) * (p->side / 4);
