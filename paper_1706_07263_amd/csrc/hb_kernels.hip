@@ -662,6 +662,8 @@ __device__ __forceinline__ bf16x8 split_pixel_operand(float u, float c, bool coo
     return b;
 }
 
+constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
+
 // A wave takes a compact 8-wide tile of LL pixels (PW / 8 rows), four waves
 // of a workgroup stack vertically; compact tiles keep the wave's observations
 // close together, which is what the skipping test below relies on.
@@ -678,8 +680,15 @@ __device__ __forceinline__ WaveWork wave_work(const PosteriorArgs &a) {
     WaveWork w;
     const int wave = threadIdx.x >> 6;
     const int S = a.split;
-    w.split = blockIdx.x % S;
-    const int chunk = blockIdx.x / S;
+    // Workgroups are dealt to the 8 XCDs in turn; renumber them so that each
+    // XCD takes a contiguous run of tiles (neighbouring pixels keep
+    // overlapping chunks, which then stay in that XCD's L2).  The last
+    // gridDim.x % 8 workgroups keep their numbers.
+    int bid = blockIdx.x;
+    const int per_xcd = gridDim.x / kXcds;
+    if (bid < per_xcd * kXcds) bid = (bid % kXcds) * per_xcd + bid / kXcds;
+    w.split = bid % S;
+    const int chunk = bid / S;
     const int bcols = (a.wl + kWaveTileW - 1) / kWaveTileW;
     const int brows = (a.hl + 4 * TH - 1) / (4 * TH);
     const int per_frame = bcols * brows;
