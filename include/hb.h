@@ -178,9 +178,12 @@ hb_status_t hb_plan_get_timing(hb_plan_t plan, double ms[4], int64_t launches[4]
  * Synchronises the device. */
 hb_status_t hb_plan_get_work(hb_plan_t plan, int64_t *evaluated, int64_t *full);
 
-/* Intermediate buffers of the last hb_estimate_frames call, for step-by-step
- * checks.  Synchronises the device, then copies `bytes` from the start of the
- * selected buffer of frame `frame` into host memory:
+/* Intermediate buffers of the last hb_estimate_frames call, and the plan's
+ * posterior operand tables, for step-by-step checks.  Synchronises the
+ * device, then copies `bytes` from the start of the selected buffer of frame
+ * `frame` into host memory (the tables ignore `frame`, which must still lie
+ * in [0, max_batch); they need a forward model, else
+ * HB_ERR_NO_FORWARD_MODEL):
  *   HB_DEBUG_LOWPASS_OBS: float32 [2][3][LL], centred low-pass observation
  *       z_k = ybar_k - mu_ref_k (ybar = block mean of log-attenuation) as a
  *       double-float: z_k = [0][k] + [1][k] (high and low parts),
@@ -190,8 +193,24 @@ hb_status_t hb_plan_get_work(hb_plan_t plan, int64_t *evaluated, int64_t *full);
  *       directional coefficients with the low-pass coefficient set to 0; the
  *       maps are this plus the block's low-pass estimate;
  *   HB_DEBUG_LOWPASS_EST: float32 [LL][2], low-pass estimate (Hb, HbO2)
- *       per block (the block mean of the output maps). */
-typedef enum { HB_DEBUG_LOWPASS_OBS = 0, HB_DEBUG_DETAILS = 1, HB_DEBUG_LOWPASS_EST = 2 } hb_debug_buffer_t;
+ *       per block (the block mean of the output maps);
+ *   HB_DEBUG_NODE_OPERANDS: float32 [n_chunks][4][16], per 16-node chunk of
+ *       the posterior grid (n_chunks = grid nodes rounded up to whole
+ *       super-tiles / 16) the scaled, centred node coordinates 0..2
+ *       relative to their super-tile's centre, and minus their squared norm,
+ *       as [coordinate or norm][node];
+ *   HB_DEBUG_SPLIT_OPERANDS: bf16 bits (uint16) [n_chunks][4][16][8], the
+ *       MFMA node operands built from those values: for row g < 3 and
+ *       value v of node i, three bf16 parts with v1 + v2 + v3 = v exactly,
+ *       stored as (v1, v2, v1, v3, v2, v1, v3, v2); for g = 3 the norm's
+ *       parts and three ones, (n1, n2, n3, 1, 1, 1, 0, 0). */
+typedef enum {
+    HB_DEBUG_LOWPASS_OBS = 0,
+    HB_DEBUG_DETAILS = 1,
+    HB_DEBUG_LOWPASS_EST = 2,
+    HB_DEBUG_NODE_OPERANDS = 3,
+    HB_DEBUG_SPLIT_OPERANDS = 4
+} hb_debug_buffer_t;
 hb_status_t hb_debug_copy(hb_plan_t plan, int32_t which, int32_t frame, void *host_dst, size_t bytes);
 
 #ifdef __cplusplus

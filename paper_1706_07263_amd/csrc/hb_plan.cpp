@@ -778,6 +778,34 @@ hb_status_t hb_debug_copy(hb_plan_t p, int32_t which, int32_t frame, void *host_
             src = p->d_est + (size_t)frame * LL;
             avail = sizeof(float2) * LL;
             break;
+        case HB_DEBUG_NODE_OPERANDS:
+        case HB_DEBUG_SPLIT_OPERANDS: {
+            if (!p->has_model) return HB_ERR_NO_FORWARD_MODEL;
+            const int cps = (p->side / 4) * (p->side / 4);
+            const size_t n_chunks = (size_t)p->n_tiles * cps;
+            if (which == HB_DEBUG_SPLIT_OPERANDS) {
+                src = p->d_split;
+                avail = n_chunks * kSplitChunkBytes;
+                break;
+            }
+            // gather the first 64 floats of every chunk from a host copy of the table
+            if (bytes > n_chunks * 64 * sizeof(float)) return HB_ERR_INVALID_ARG;
+            if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
+            if (hipDeviceSynchronize() != hipSuccess) return HB_ERR_DEVICE;
+            const int stride = super_floats(p->side);
+            std::vector<float> table((size_t)p->n_tiles * stride);
+            if (hipMemcpy(table.data(), p->d_tiles, sizeof(float) * table.size(), hipMemcpyDeviceToHost) !=
+                hipSuccess)
+                return HB_ERR_DEVICE;
+            std::vector<float> ops(n_chunks * 64);
+            for (size_t c = 0; c < n_chunks; ++c) {
+                const size_t si = c / cps, ci = c % cps;
+                const float *C = &table[si * stride + kSupHdr + kMaxProbes * kProbeFloats + ci * kChunkFloats];
+                std::memcpy(&ops[c * 64], C, 64 * sizeof(float));
+            }
+            std::memcpy(host_dst, ops.data(), bytes);
+            return HB_OK;
+        }
         default:
             return HB_ERR_INVALID_ARG;
     }

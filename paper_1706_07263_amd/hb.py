@@ -38,6 +38,7 @@ HB_ERR_BATCH = -7
 HB_F32, HB_F16, HB_BF16 = 0, 1, 2
 HB_LOWPASS_BAYES, HB_LOWPASS_TIKHONOV = 0, 1
 HB_DEBUG_LOWPASS_OBS, HB_DEBUG_DETAILS, HB_DEBUG_LOWPASS_EST = 0, 1, 2
+HB_DEBUG_NODE_OPERANDS, HB_DEBUG_SPLIT_OPERANDS = 3, 4
 
 DTYPES = {"f32": HB_F32, "f16": HB_F16, "bf16": HB_BF16}
 

@@ -223,6 +223,39 @@ def test_posterior_kernel_choice(torch_cuda, grid, sigma, kernel):
         assert p.info()["posterior_kernel"] == kernel
 
 
+@pytest.mark.parametrize("grid", [32, 100, 256])
+def test_split_operands_are_exact(torch_cuda, grid):
+    """The MFMA kernel's node operands are exact three-part bf16 splits of the
+    FP32 node coordinates and squared-norm entries (so its logit has every
+    product of the FP32 values except the smallest, u3 v3), in the slot order
+    the header documents; grid 100 has padded chunks."""
+    from paper_1706_07263_amd import hb
+    d = hb.make_desc(64, 64, grid_thb=grid, grid_so2=grid)
+    with hb.Plan(d, 0) as p:
+        p.set_forward_model(synth.spectra())
+        side = min(32, max(4, 4 * (grid // 32)))          # super-tile side
+        n_chunks = p.info()["n_tiles"] * (side // 4) ** 2
+        node = hb.hb_debug_copy(p.handle, hb.HB_DEBUG_NODE_OPERANDS, 0, np.zeros((n_chunks, 4, 16), np.float32))
+        bits = hb.hb_debug_copy(p.handle, hb.HB_DEBUG_SPLIT_OPERANDS, 0,
+                                np.zeros((n_chunks, 4, 16, 8), np.uint16))
+    f = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    v = node.astype(np.float64)
+    c = f[:, :3]
+    # (v1, v2, v1, v3, v2, v1, v3, v2)
+    assert np.array_equal(c[..., 0], c[..., 2]) and np.array_equal(c[..., 0], c[..., 5])
+    assert np.array_equal(c[..., 1], c[..., 4]) and np.array_equal(c[..., 1], c[..., 7])
+    assert np.array_equal(c[..., 3], c[..., 6])
+    assert np.array_equal(c[..., 0] + c[..., 1] + c[..., 3], v[:, :3])
+    # (n1, n2, n3, 1, 1, 1, 0, 0)
+    n = f[:, 3]
+    assert np.array_equal(n[..., 0] + n[..., 1] + n[..., 2], v[:, 3])
+    assert np.all(n[..., 3:6] == 1.0) and np.all(n[..., 6:] == 0.0)
+    # a genuine split: each part is at most half a bf16 unit of the one before
+    for parts in (c[..., [0, 1, 3]], n[..., :3]):
+        for k in (1, 2):
+            assert np.all(np.abs(parts[..., k]) <= np.abs(parts[..., k - 1]) * 2.0 ** -8)
+
+
 @pytest.mark.parametrize("grid", [24, 32, 40])
 def test_parity_near_the_kernel_threshold(torch_cuda, grid):
     w = synth.config1()
