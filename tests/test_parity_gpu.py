@@ -84,6 +84,9 @@ def test_steps_match_oracle(torch_cuda):
     (32, 64, 4, (9, 9)),
     (64, 96, 5, (8, 16)),
     (8, 3000, 0, (12, 10)),        # posterior on every pixel, several chunks
+    (64, 64, 1, (100, 130)),       # 12-node super-tiles (9 chunks), padded edges
+    (64, 64, 1, (230, 200)),       # 24-node super-tiles (36 chunks), padded edges
+    (64, 64, 2, (300, 250)),       # 28-node super-tiles (49 chunks), padded edges
 ])
 def test_shapes_levels_and_ragged_grids(torch_cuda, h, w, levels, grid):
     fr, _, _ = synth.single_frame(h, w, config=60, stream=levels)
