@@ -57,9 +57,12 @@ constexpr int kSplitChunkBytes = 64 * kSplitLaneBytes;
 // of the squared super-tile radius R^2 (scaled units), and a coarse grid
 // (node spacing h in uM of Hb/HbO2) turns a logit error into an estimate error
 // of about R^2 h u with little averaging.  The MFMA kernel is used when
-// R^2 h <= kMfmaPrecisionBudget, the direct kernel otherwise (both meet the
-// parity tolerance; the bound was set from the measured parity errors).
-constexpr double kMfmaPrecisionBudget = 1000.0;
+// R^2 h <= kMfmaPrecisionBudget, the direct kernel otherwise.  Measured
+// against the oracle (64 x 64 frame, grids 32..256, sigma 0.002..0.01): up
+// to R^2 h = 700 the MFMA kernel's largest error was 4.6e-5 uM; between 800
+// and 1000 it reached 8.0e-5 uM (sigma 0.004 on a 256 x 256 grid), too
+// close to the 1e-4 uM tolerance.
+constexpr double kMfmaPrecisionBudget = 700.0;
 
 // Posterior chunk skipping.  exp2 of anything below -kExactSkipLog2 is exactly
 // 0 in float32 (the smallest subnormal is 2^-149; the margin covers rounding

@@ -215,7 +215,8 @@ def test_null_maps_are_skipped(torch_cuda):
 
 @pytest.mark.parametrize("grid,sigma,kernel", [(256, 0.01, "mfma"), (128, 0.01, "mfma"), (512, 0.01, "mfma"),
                                                (64, 0.01, "mfma"), (32, 0.01, "mfma"), (16, 0.01, "direct"),
-                                               (48, 0.001, "direct")])
+                                               (48, 0.001, "direct"), (256, 0.005, "mfma"),
+                                               (256, 0.004, "direct"), (128, 0.005, "direct")])
 def test_posterior_kernel_choice(torch_cuda, grid, sigma, kernel):
     """Fine grids take the MFMA kernel, grids too coarse for its expanded
     logit take the direct one (both are covered by the parity tests above)."""
@@ -257,6 +258,19 @@ def test_split_operands_are_exact(torch_cuda, grid):
     for parts in (c[..., [0, 1, 3]], n[..., :3]):
         for k in (1, 2):
             assert np.all(np.abs(parts[..., k]) <= np.abs(parts[..., k - 1]) * 2.0 ** -8)
+
+
+@pytest.mark.parametrize("grid,sigma", [(256, 0.005), (256, 0.004), (128, 0.007), (128, 0.005)])
+def test_parity_near_the_kernel_threshold_fine_grids(torch_cuda, grid, sigma):
+    """Narrow posteriors on fine grids, on both sides of the MFMA kernel's
+    precision threshold (the MFMA cases are the least precise it takes)."""
+    w = synth.config1()
+    s = _settings(grid=grid, sigma=sigma)
+    run = hbtest.GpuRun(64, 64, s)
+    gpu = run(w.frames)
+    err = hbtest.assert_maps_close(gpu, hbtest.run_oracle(w.frames, "f32", s), f"G{grid} sigma {sigma}")
+    print(f"G{grid} sigma {sigma}", run.plan.info()["posterior_kernel"], err)
+    run.close()
 
 
 @pytest.mark.parametrize("grid", [24, 32, 40])
