@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--no-table1", action="store_true", help="skip the Table 1 speed-ratio analogue")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--sequence", type=int, default=0,
+                    help="only time the first N frames of the video, all resident in HBM, "
+                         "at batch 1, 4 and 16 (one JSON line)")
     return ap.parse_args()
 
 
@@ -247,6 +250,48 @@ def serving(a):
     return out
 
 
+def sequence(a, torch, hb, synth, hbtest):
+    """Frames 0..N-1 of the 1920x1080 video rendered once and kept in HBM,
+    then estimated in order at batch 1, 4 and 16 (the last call of a pass
+    takes what is left), each pass timed on the host clock between device
+    synchronisations after one untimed call."""
+    H, W, n = 1080, 1920, a.sequence
+    dev = torch.device("cuda:0")
+    parts = []
+    for s0 in range(0, n, 32):
+        idx = list(range(s0, min(n, s0 + 32)))
+        parts.append(hbtest.to_device(render_video(idx, a.dtype, workers=16), a.dtype))
+        log(f"rendered frames {idx[0]}..{idx[-1]}", a.quiet)
+    frames = torch.cat(parts)
+    del parts
+    settings = dict(synth.config3((0,), dtype=a.dtype).plan)
+    fps, mpx = {}, {}
+    for B in (1, 4, 16):
+        maps = [torch.empty((B, H, W), device=dev, dtype=torch.float32) for _ in range(4)]
+        desc = hb.make_desc(W, H, levels=a.levels, dtype=a.dtype, max_batch=B, grid_thb=a.grid,
+                            grid_so2=a.grid, lam=settings["lam"], sigma=settings["sigma"], grid_split=a.split)
+        with hb.Plan(desc, 0) as plan:
+            plan.set_forward_model(synth.spectra())
+            stream = torch.cuda.Stream(dev)
+            with torch.cuda.stream(stream):
+                plan.estimate(frames[:B], maps, stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                for s0 in range(0, n, B):
+                    plan.estimate(frames[s0:s0 + B], maps, stream)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        fps[str(B)] = round(n / dt, 2)
+        mpx[str(B)] = round(n * H * W / dt / 1e6, 2)
+        log(f"batch {B}: {n} frames in {dt:.3f} s", a.quiet)
+    print(json.dumps({"metric": "frames/s and Mpixel/s over the whole video sequence", "frames": n,
+                      "frames_per_s": fps, "mpixel_per_s": mpx, "dtype": a.dtype, "data": "synthetic",
+                      "config": {"workload": f"1920x1080 video frames 0..{n - 1}, {a.levels} Haar levels, "
+                                             f"{a.grid}x{a.grid} THb x SO2 posterior grid, {a.dtype} frames",
+                                 "frames_resident_in_hbm": True}}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -269,6 +314,9 @@ def main():
         __graft_entry__.build()
     from paper_1706_07263_amd import hb, synth
     from tests import hbtest
+    if a.sequence:
+        sequence(a, torch, hb, synth, hbtest)
+        return
 
     B = a.batch
     H, W = 1080, 1920
