@@ -295,7 +295,7 @@ def sequence(a, torch, hb, synth, hbtest):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported "
               "(each frame and each stream is independent: see the sharding notes)", file=sys.stderr)
         sys.exit(2)
     import torch
