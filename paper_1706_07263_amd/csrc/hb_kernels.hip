@@ -663,6 +663,7 @@ __device__ __forceinline__ bf16x8 split_pixel_operand(float u, float c, bool coo
 }
 
 constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
+constexpr int kOrderSquare = 8;
 
 // A wave takes a compact 8-wide tile of LL pixels (PW / 8 rows), four waves
 // of a workgroup stack vertically; compact tiles keep the wave's observations
@@ -694,8 +695,24 @@ __device__ __forceinline__ WaveWork wave_work(const PosteriorArgs &a) {
     const int per_frame = bcols * brows;
     w.f = chunk / per_frame;
     const int t = chunk % per_frame;
-    w.r0 = (t / bcols) * 4 * TH + wave * TH;
-    w.c0 = (t % bcols) * kWaveTileW;
+    // Blocks in squares of kOrderSquare x kOrderSquare (bands of that many
+    // block rows, squares left to right, row-major inside a square): the
+    // workgroups an XCD runs at once then cover a compact part of the frame.
+    const int band = t / (kOrderSquare * bcols), in_band = t % (kOrderSquare * bcols);
+    const int R = min(kOrderSquare, brows - band * kOrderSquare);
+    const int full = bcols / kOrderSquare;          // full-width squares in the band
+    int br, bc;
+    if (in_band < full * R * kOrderSquare) {
+        const int sq = in_band / (R * kOrderSquare), o = in_band % (R * kOrderSquare);
+        br = o / kOrderSquare;
+        bc = sq * kOrderSquare + o % kOrderSquare;
+    } else {
+        const int wl = bcols - full * kOrderSquare, o = in_band - full * R * kOrderSquare;
+        br = o / wl;
+        bc = full * kOrderSquare + o % wl;
+    }
+    w.r0 = (band * kOrderSquare + br) * 4 * TH + wave * TH;
+    w.c0 = bc * kWaveTileW;
     w.s0 = (int)((long long)a.n_supers * w.split / S);
     w.s1 = (int)((long long)a.n_supers * (w.split + 1) / S);
     return w;
