@@ -34,8 +34,8 @@ EXPS_PER_PAIR = 1
 # profiles/hot_path_1080p_L2_G256_b16.md, valid for the device sources whose
 # combined sha256 (kernel_source_sha) starts with PROFILED_KERNEL_SHA; reported
 # as null for any other source or workload.
-PROFILED_KERNEL_SHA = "06a51450c738a229"
-PROFILED_POSTERIOR_TRAFFIC = 1234.86e6
+PROFILED_KERNEL_SHA = "bd2ead1ae8648636"
+PROFILED_POSTERIOR_TRAFFIC = 1236.93e6
 KERNEL_SOURCES = ("hb_kernels.hip", "hb_internal.h", "hb_df.h")
 
 

@@ -78,7 +78,6 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x3 __attribute__((ext_vector_type(3)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 // Word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format).
 constexpr int kBufferWord3 = 0x00020000;
 
