@@ -49,3 +49,47 @@ def test_grid_is_inclusive_product_grid(model):
     assert np.allclose(so2[0], [0.3, 0.65, 1.0])
     for g in (0, 7, 14):
         assert np.allclose(mu[g], orc.mu(model, *c[g]), rtol=0, atol=0)
+
+
+def _transmittance(spectra, j, hb, hbo2, path_cm):
+    """Beer-Lambert transmittance at one wavelength (natural-log extinction)."""
+    return np.exp(-path_cm * (spectra.eps_hb[j] * hb + spectra.eps_hbo2[j] * hbo2))
+
+
+@pytest.mark.parametrize("c", [(40.0, 80.0), (150.0, 10.0), (5.0, 3.0)])
+def test_two_wavelength_channel_averages_transmittances(spectra, c):
+    """Camera intensities are a linear map of the spectral intensities (Method,
+    Eq. 3), and each wavelength attenuates by Beer-Lambert: a channel that sees
+    two wavelengths with equal sensitivity receives the mean of their
+    transmittances, exp(-mu) = (T1 + T2) / 2 (not their geometric mean, which
+    mixing in the log domain would give)."""
+    n = spectra.eps_hb.size
+    j1, j2, j3 = 4, 50, 30          # 420 nm (strong absorption), 650 nm (weak), 550 nm
+    resp = np.zeros((3, n))
+    resp[0, [j1, j2]] = 2.5          # equal weights, any scale
+    resp[1, [j1, j3]] = [1.0, 3.0]   # weights 1/4 and 3/4
+    resp[2, [j2, j3]] = [0.2, 0.2]
+    L = 0.1
+    m = orc.Model(spectra.eps_hb, spectra.eps_hbo2, resp, L)
+    hb, hbo2 = c
+    t1, t2, t3 = (_transmittance(spectra, j, hb, hbo2, L) for j in (j1, j2, j3))
+    got = np.exp(-orc.mu(m, hb, hbo2))
+    want = np.array([(t1 + t2) / 2, 0.25 * t1 + 0.75 * t3, (t2 + t3) / 2])
+    assert np.allclose(got, want, rtol=1e-14, atol=0)
+    # the two transmittances differ enough for the distinction to matter
+    assert abs(t1 - t2) > 1e-3
+
+
+@pytest.mark.parametrize("alpha", [0.25, 0.6])
+def test_channel_transmittance_is_linear_in_the_response(spectra, alpha):
+    """Superposition (Method, Eq. 3: I_RGB = C I_lambda): a channel whose
+    normalised sensitivity is the convex mix a s_R + (1 - a) s_B of two others
+    sees the same mix of their transmittances exp(-mu_R) and exp(-mu_B)."""
+    resp = np.asarray(spectra.response, dtype=np.float64)
+    s = resp / resp.sum(axis=1, keepdims=True)
+    mixed = np.stack([s[0], s[2], alpha * s[0] + (1 - alpha) * s[2]])
+    m = orc.Model(spectra.eps_hb, spectra.eps_hbo2, mixed, spectra.path_length_cm)
+    for hb, hbo2 in [(20.0, 90.0), (120.0, 60.0), (60.0, 0.0)]:
+        T = np.exp(-orc.mu(m, hb, hbo2))
+        assert abs(T[2] - (alpha * T[0] + (1 - alpha) * T[1])) <= 1e-14 * T[2]
+        assert abs(T[0] - T[1]) > 1e-3
