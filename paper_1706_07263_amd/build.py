@@ -1,4 +1,6 @@
-"""Build the gfx950 C-ABI library ``libhbgpu.so`` in-tree with hipcc."""
+"""Build the gfx950 C-ABI library ``libhbgpu.so`` in-tree with hipcc, and the
+instruction-mix microbenchmarks ``libhbceiling.so`` that the benchmark uses
+for the posterior's roofline."""
 from __future__ import annotations
 
 import os
@@ -12,6 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhbgpu.so")
 SOURCES = ["hb_kernels.hip", "hb_plan.cpp"]
+LIB_CEILING = os.path.join(PKG, "libhbceiling.so")
+CEILING_SOURCES = ["hb_ceiling.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -30,11 +34,11 @@ def hipcc() -> str:
     return path
 
 
-def build(verbose: bool = False) -> str:
+def _build_lib(sources, lib: str, verbose: bool) -> str:
     objs = []
     build_dir = os.path.join(PKG, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    for src in SOURCES:
+    for src in sources:
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"]
         cmd = [hipcc(), *HIPCC_FLAGS, *lang, "-I", INCLUDE, "-I", CSRC, "-c",
@@ -48,13 +52,19 @@ def build(verbose: bool = False) -> str:
         if verbose and err.strip():
             print(err, file=sys.stderr)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """Build both libraries; returns the path of the C-ABI library."""
+    _build_lib(CEILING_SOURCES, LIB_CEILING, verbose)
+    return _build_lib(SOURCES, LIB, verbose)
 
 
 if __name__ == "__main__":
