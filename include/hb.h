@@ -81,14 +81,17 @@ typedef struct {
                                    Method, before Eq. 9): residuals are projected onto the
                                    plane orthogonal to (1,1,1).  0 (default) = off.  Only
                                    affects HB_LOWPASS_BAYES; any other value is rejected. */
-    double posterior_tolerance; /* uM, >= 0.  The posterior skips 4x4-node grid chunks whose
-                                   weights are all provably below 2^-T of the pixel's
+    double posterior_tolerance; /* uM, finite.  > 0: the posterior skips 4x4-node grid chunks
+                                   whose weights are all provably below 2^-T of the pixel's
                                    reference weight, with T chosen so that the skipped
                                    weights move the posterior mean of Hb and HbO2 by at
                                    most this much (bound: 2 G 2^-T thb_max, G grid nodes;
-                                   the T in use is reported by hb_plan_get_info).  0 = skip
-                                   only chunks whose float32 weights are exactly zero.
-                                   Default 1e-6 uM, 1% of the FP32 parity tolerance.     */
+                                   the T in use is reported by hb_plan_get_info).
+                                   0: skip only chunks whose float32 weights are all exactly
+                                   zero (T = 160; results equal those of no skipping, bit
+                                   for bit).  < 0: skip nothing (every chunk that holds a
+                                   grid node is evaluated; T = +inf).  Default 1e-6 uM, 1%
+                                   of the FP32 parity tolerance.                          */
 } hb_plan_desc_t;
 
 /* Camera sensitivities and attenuation spectra (the camera matrix C and the
@@ -119,7 +122,8 @@ typedef struct {
     int32_t n_tiles;      /* grid super-tiles                                                           */
     int32_t posterior_kernel; /* 0 = MFMA logits, 1 = direct VALU (grids too coarse for the former)     */
     int64_t n_nodes;
-    double skip_log2;     /* T: chunks whose logit bound lies more than T below the reference are skipped */
+    double skip_log2;     /* T: chunks whose logit bound lies more than T below the reference are skipped
+                             (+inf: nothing is skipped)                                                   */
     double skip_bound;    /* uM, the stated bound on the posterior-mean change from skipping (0: exact)  */
 } hb_plan_info_t;
 
@@ -145,7 +149,9 @@ hb_status_t hb_set_forward_model(hb_plan_t plan, const hb_forward_model_t *fm);
 hb_status_t hb_estimate_frames(hb_plan_t plan, const void *d_frames, int32_t n_frames,
                                const hb_maps_t *d_out, void *stream);
 
-/* Synchronise the device and free the plan.  NULL is accepted. */
+/* Wait for the plan's last hb_estimate_frames call (not for other streams, and
+ * not for replays of graphs the caller captured: those are the caller's to wait
+ * for), then free the plan's device memory.  NULL is accepted. */
 hb_status_t hb_destroy(hb_plan_t plan);
 
 /* Static description of a status code (never NULL). */
@@ -170,12 +176,12 @@ hb_status_t hb_plan_get_timing(hb_plan_t plan, double ms[4], int64_t launches[4]
 
 /* Posterior work of the calls made since the last hb_plan_set_timing
  * (counted only while timing is enabled): `evaluated` = (LL pixel, grid node)
- * pairs the posterior kernel actually evaluated, `full` = LL pixels x grid
- * nodes of those calls.  The MFMA kernel leaves out 16-node chunks whose
- * weights are exactly zero in float32 for every pixel of a wave (their box
- * bound is more than 160 below each pixel's reference logit), so
- * evaluated <= full while the results are unchanged bit for bit.
- * Synchronises the device. */
+ * pairs the posterior kernel actually evaluated (whole 16-node chunks for
+ * every pixel of a wave), `full` = LL pixels x grid nodes of those calls.
+ * The kernels leave out chunks whose weights lie more than T below every
+ * pixel's reference weight (posterior_tolerance above), so evaluated <= full;
+ * the results then move by at most the plan's stated skip_bound (exactly 0
+ * for T = 160 and for no skipping).  Synchronises the device. */
 hb_status_t hb_plan_get_work(hb_plan_t plan, int64_t *evaluated, int64_t *full);
 
 /* Intermediate buffers of the last hb_estimate_frames call, and the plan's

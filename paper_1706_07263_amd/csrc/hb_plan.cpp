@@ -54,6 +54,7 @@ struct hb_plan_s {
     float scale = 1.0f;
     float skip_log2 = kExactSkipLog2;
 
+    hipEvent_t done = nullptr;       // recorded after each uncaptured hb_estimate_frames
     bool timing = false;
     std::vector<hipEvent_t> events;  // 4 per recorded call
     int timed_calls = 0;
@@ -91,7 +92,7 @@ hb_status_t check_desc(const hb_plan_desc_t *d) {
     if (d->lowpass != HB_LOWPASS_BAYES && d->lowpass != HB_LOWPASS_TIKHONOV) return HB_ERR_INVALID_ARG;
     if (d->grid_split < 0 || d->grid_split > 256) return HB_ERR_INVALID_ARG;
     if (d->illumination != 0 && d->illumination != 1) return HB_ERR_INVALID_ARG;
-    if (!is_finite(d->posterior_tolerance) || d->posterior_tolerance < 0) return HB_ERR_INVALID_ARG;
+    if (!is_finite(d->posterior_tolerance)) return HB_ERR_INVALID_ARG;
     return HB_OK;
 }
 
@@ -145,6 +146,7 @@ void free_plan(hb_plan_s *p) {
     (void)hipFree(p->d_est);
     (void)hipFree(p->d_work);
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+    if (p->done) (void)hipEventDestroy(p->done);
     delete p;
 }
 
@@ -462,6 +464,10 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_est, sizeof(float2) * nb * LL);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_work, sizeof(unsigned long long));
     if (st == HB_OK && hipMemset(p->d_work, 0, sizeof(unsigned long long)) != hipSuccess) st = HB_ERR_DEVICE;
+    if (st == HB_OK && hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) {
+        p->done = nullptr;
+        st = HB_ERR_DEVICE;
+    }
     if (st != HB_OK) {
         free_plan(p);
         return st;
@@ -472,6 +478,8 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     if (desc->posterior_tolerance > 0) {
         const double t = std::ceil(std::log2(2.0 * (double)p->n_nodes * desc->thb_max / desc->posterior_tolerance));
         p->skip_log2 = (float)std::min<double>(kExactSkipLog2, std::max<double>(kMinSkipLog2, t));
+    } else if (desc->posterior_tolerance < 0) {
+        p->skip_log2 = INFINITY;   // no skipping: every chunk holding a grid node is evaluated
     }
     p->info.skip_log2 = p->skip_log2;
     *out = p;
@@ -502,6 +510,10 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
         for (int j = 0; j < n; ++j) model.resp[k * n + j] /= sum;
     }
     if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
+    // From here on the plan's model state is being replaced: until every step
+    // below has succeeded the plan has no model, so a failed replacement can
+    // never leave new device values next to old tables.
+    p->has_model = false;
 
     const hb_plan_desc_t &d = p->desc;
     double ref_thb = d.ref_thb, ref_so2 = d.ref_so2;
@@ -691,6 +703,10 @@ hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_fram
     ra.so2 = d_out->so2;
     if (!fused && launch_recompose(n_frames, ra, s) != hipSuccess) return HB_ERR_DEVICE;
     if (mark(3) != hipSuccess) return HB_ERR_DEVICE;
+    // Completion marker for hb_destroy (not recorded into a graph under capture).
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return HB_ERR_DEVICE;
+    if (cap == hipStreamCaptureStatusNone && hipEventRecord(p->done, s) != hipSuccess) return HB_ERR_DEVICE;
     p->last_frames = n_frames;
     return HB_OK;
 }
@@ -698,7 +714,8 @@ hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_fram
 hb_status_t hb_destroy(hb_plan_t p) {
     if (!p) return HB_OK;
     hb_status_t st = HB_OK;
-    if (set_device(p->device) != HB_OK || hipDeviceSynchronize() != hipSuccess) st = HB_ERR_DEVICE;
+    // Wait for the plan's last uncaptured call only (other streams keep running).
+    if (set_device(p->device) != HB_OK || hipEventSynchronize(p->done) != hipSuccess) st = HB_ERR_DEVICE;
     free_plan(p);
     return st;
 }

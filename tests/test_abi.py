@@ -108,7 +108,7 @@ BAD = [
     (dict(lowpass=2), "HB_ERR_INVALID_ARG"),
     (dict(grid_split=-1), "HB_ERR_INVALID_ARG"),
     (dict(illumination=2), "HB_ERR_INVALID_ARG"),
-    (dict(posterior_tolerance=-1.0), "HB_ERR_INVALID_ARG"),
+    (dict(posterior_tolerance=-math.inf), "HB_ERR_INVALID_ARG"),   # negative finite = no skipping
     (dict(posterior_tolerance=float("nan")), "HB_ERR_INVALID_ARG"),
 ]
 
