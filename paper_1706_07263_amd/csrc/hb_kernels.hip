@@ -1108,12 +1108,14 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
     }
     // Result layout: lane (lp, lk) holds pixel b*16 + lp and the four nodes
     // of chunk row lk; its sums run over those nodes of every kept chunk.
-    float anc_hb[PB], anc_ox[PB], R0[PB], R1[PB], R2[PB];
+    // Sums across super-tiles carry Kahan compensation terms K0..K2.
+    float anc_hb[PB], anc_ox[PB], R0[PB], R1[PB], R2[PB], K0[PB], K1[PB], K2[PB];
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
         anc_hb[b] = __shfl(ref.ahb, b * 16 + lp);
         anc_ox[b] = __shfl(ref.aox, b * 16 + lp);
         R0[b] = R1[b] = R2[b] = 0.0f;
+        K0[b] = K1[b] = K2[b] = 0.0f;
     }
 
     const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -1211,9 +1213,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
         const float chb = T[6], cox = T[7];
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
-            R0[b] += L0[b];
-            R1[b] += fmaf(chb - anc_hb[b], L0[b], L1[b]);
-            R2[b] += fmaf(cox - anc_ox[b], L0[b], L2[b] - L1[b]);   // HbO2 = THb - Hb
+            kahan_add(R0[b], K0[b], L0[b]);
+            kahan_add(R1[b], K1[b], fmaf(chb - anc_hb[b], L0[b], L1[b]));
+            kahan_add(R2[b], K2[b], fmaf(cox - anc_ox[b], L0[b], L2[b] - L1[b]));   // HbO2 = THb - Hb
         }
       }
     }
