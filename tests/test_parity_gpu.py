@@ -558,3 +558,84 @@ def test_binding_rejects_mismatched_tensors(torch_cuda):
             assert e.value.status == status
         p.estimate(ok, [None, maps[1], None, None])
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("grid", [256, 16])
+def test_no_skipping_equals_exact_skipping(torch_cuda, grid):
+    """A negative posterior tolerance evaluates every chunk of the grid; exact
+    skipping (tolerance 0) leaves out only chunks whose float32 weights are
+    all zero, so both give the same maps bit for bit, and both match the
+    oracle.  Grid 256 takes the MFMA kernel, grid 16 the direct one."""
+    from paper_1706_07263_amd import hb
+    fr, _, _ = synth.single_frame(128, 192, config=64)
+    s = _settings(levels=2, grid=grid)
+    out, work = {}, {}
+    for t in (-1.0, 0.0):
+        run = hbtest.GpuRun(192, 128, dict(s, posterior_tolerance=t))
+        info = run.plan.info()
+        assert info["skip_bound"] == 0.0
+        assert info["skip_log2"] == (math.inf if t < 0 else 160.0)
+        hb.hb_plan_set_timing(run.plan.handle, True)
+        out[t] = run(fr[None])
+        work[t] = hb.hb_plan_get_work(run.plan.handle)
+        hb.hb_plan_set_timing(run.plan.handle, False)
+        kernel = info["posterior_kernel"]
+        run.close()
+    assert kernel == ("mfma" if grid == 256 else "direct")
+    evaluated, full = work[-1.0]
+    assert evaluated == full == 32 * 48 * grid * grid
+    assert work[0.0][0] <= evaluated
+    assert np.array_equal(out[-1.0], out[0.0], equal_nan=True)
+    err = hbtest.assert_maps_close(out[-1.0], hbtest.run_oracle(fr[None], "f32", s), f"no skipping G{grid}")
+    print(f"G{grid} {kernel}: exact skipping evaluates {work[0.0][0] / full:.3f} of the grid; errors {err}")
+
+
+def test_failed_model_replacement_leaves_no_model(torch_cuda):
+    """A model replacement that fails (here: a singular Tikhonov system) leaves
+    the plan without a model: estimates are refused until a model is set
+    again, and setting the first model again gives the first results."""
+    import torch
+    from paper_1706_07263_amd import hb
+    w = synth.config1()
+    sp = synth.spectra()
+    run = hbtest.GpuRun(64, 64, dict(w.plan, lam=0.0))
+    first = run(w.frames)
+    with pytest.raises(hb.HbError) as e:
+        hb.hb_set_forward_model(run.plan.handle, sp.eps_hb, 2 * sp.eps_hb, sp.response, 0.1)
+    assert e.value.status == hb.HB_ERR_ILL_POSED
+    fr = torch.from_numpy(w.frames).cuda()
+    maps = [torch.zeros((1, 64, 64), device="cuda") for _ in range(4)]
+    with pytest.raises(hb.HbError) as e:
+        run.plan.estimate(fr, maps)
+    assert e.value.status == hb.HB_ERR_NO_FORWARD_MODEL
+    with pytest.raises(hb.HbError) as e:
+        run.plan.info()
+    assert e.value.status == hb.HB_ERR_NO_FORWARD_MODEL
+    run.plan.set_forward_model(sp)
+    again = run(w.frames)
+    assert np.array_equal(first, again, equal_nan=True)
+    run.close()
+
+
+def test_destroy_waits_for_the_plans_stream(torch_cuda):
+    """hb_destroy waits for the plan's last call on its own stream: maps
+    written by a call still in flight are complete after it returns."""
+    import torch
+    from paper_1706_07263_amd import hb
+    w = synth.config1()
+    ref = hbtest.GpuRun(64, 64, w.plan)
+    want = ref(w.frames)
+    ref.close()
+    fr = torch.from_numpy(np.repeat(w.frames, 8, axis=0)).cuda()
+    maps = [torch.full((8, 64, 64), float("nan"), device="cuda") for _ in range(4)]
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    plan = hb.Plan(hb.make_desc(64, 64, levels=1, max_batch=8, grid_thb=32, grid_so2=32,
+                                lam=w.plan["lam"], sigma=w.plan["sigma"]), 0)
+    plan.set_forward_model(synth.spectra())
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        plan.estimate(fr, maps, side)
+    plan.close()   # returns after the call on `side` has finished
+    got = np.stack([m.cpu().numpy() for m in maps], axis=1)
+    assert np.array_equal(got, np.repeat(want, 8, axis=0), equal_nan=True)
