@@ -7,13 +7,18 @@ THb x SO2 grid, inverse Haar and maps), frames already resident in HBM.
 Prints one JSON line with frames/s (value), Mpixel/s, the roofline of the
 dominant kernel (the posterior) from per-kernel HIP events recorded on the
 launch stream, and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+workload.  Further legs (``--legs``) add the posterior without skipping and
+with exact skipping, the instruction-mix ceilings, half-precision storage,
+the stereo 1280x1024 pair with a 512x512 grid, a batch sweep, the Table 1
+analogue, frames from host memory and the 16-stream serving runs.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
+import subprocess
 import sys
 import time
 
@@ -23,17 +28,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "frames/s + Mpixel/s at 1920x1080 on 1 GPU; p99 frame latency, 16 streams"
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+LEGS = ("main", "ceiling", "modes", "fp16", "config4", "sweep", "table1", "pcie", "serve", "cpu")
+
 # Algorithmic operations per (LL pixel, grid node) pair of the posterior:
-# 3 sub + 3 mul + 2 add (squared distance), 1 mul (-1/(2 sigma^2)), 1 sub (max
-# offset), 1 add + 2 mul + 2 add (three moments) = 15 flops, plus one exp.
+# 3 sub + 3 mul + 2 add (squared distance), 1 mul (-1/(2 sigma^2)), 1 sub (the
+# reference), 1 add + 2 mul + 2 add (three moments) = 15 flops, plus one exp.
+# The MFMA kernel forms the first 10 (the logit) on the matrix cores from
+# exact bf16 splits and the 5 moment flops on the VALU.
 FLOPS_PER_PAIR = 15
+FLOPS_PER_PAIR_MFMA = 10
+FLOPS_PER_PAIR_VALU = 5
 EXPS_PER_PAIR = 1
+FP32_VECTOR_PEAK_TFLOPS = 157.3        # packed FP32 (not used by this build)
+FP32_UNPACKED_PEAK_TFLOPS = 78.65      # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+# Issue ceiling of the posterior's chunk evaluation (one 16-node chunk against
+# one 16-pixel block = 256 pairs) on one SIMD, from the chip's unit counts at
+# 2.4 GHz: the bf16 16x16x32 MFMA takes 16 cycles (2.5 PFLOP/s dense bf16 =
+# 1024 SIMDs x 1024 flops/cycle), each of the 9 FP32 VALU instructions takes
+# 4 (16 lanes per SIMD for unpacked FP32), each of the 4 v_exp_f32 takes 8
+# (transcendentals issue at half the FMA rate, measured by the `exp`
+# microbenchmark of the ceiling leg); the three do not overlap in one SIMD
+# (the `mfma_fma` and `exp_fma` microbenchmarks).
+MFMA_CYCLES, FMA_CYCLES, EXP_CYCLES = 16, 4, 8
+CHUNK_BLOCK_CYCLES = MFMA_CYCLES + 4 * EXP_CYCLES + 9 * FMA_CYCLES      # 84
+N_SIMD, CLOCK_HZ = 1024, 2.4e9
+CEILING_PAIRS_PER_S = 256 * N_SIMD * CLOCK_HZ / CHUNK_BLOCK_CYCLES      # 7.49e12
+CEILING_TFLOPS = CEILING_PAIRS_PER_S * FLOPS_PER_PAIR / 1e12           # 112.3
 # HBM bytes per posterior launch of the default workload (16 frames), from the
-# rocprofv3 FETCH_SIZE/WRITE_SIZE runs summarised in
-# profiles/hot_path_1080p_L2_G256_b16.md, valid for the device sources whose
-# combined sha256 (kernel_source_sha) starts with PROFILED_KERNEL_SHA; reported
-# as null for any other source or workload.
+# rocprofv3 FETCH_SIZE/WRITE_SIZE runs summarised in profiles/, valid for the
+# device sources whose combined sha256 (kernel_source_sha) starts with
+# PROFILED_KERNEL_SHA; reported as null for any other source or workload.
 PROFILED_KERNEL_SHA = "bd2ead1ae8648636"
 PROFILED_POSTERIOR_TRAFFIC = 1236.93e6
 KERNEL_SOURCES = ("hb_kernels.hip", "hb_internal.h", "hb_df.h")
@@ -48,7 +72,7 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -58,25 +82,44 @@ def parse():
     ap.add_argument("--levels", type=int, default=2)
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--split", type=int, default=0)
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated legs to run besides the timed workload: " + ",".join(LEGS[1:]) +
+                         " ('all' = every leg, 'main' = only the timed workload)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target CPU time of the oracle sample (0 = skip)")
+                    help="target CPU time of the oracle sample on all host threads (0 = skip)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
-                    help="duration of the 16-stream serving run (0 = skip)")
+                    help="duration of each 16-stream serving run (0 = skip)")
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-budget-gib", type=float, default=48.0)
-    ap.add_argument("--no-table1", action="store_true", help="skip the Table 1 speed-ratio analogue")
+    ap.add_argument("--serve-sources", type=int, default=4, help="distinct pre-rendered frames per class")
+    ap.add_argument("--serve-target-busy", type=float, default=0.7,
+                    help="lane busy fraction the loaded serving run aims at")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--sequence", type=int, default=0,
                     help="only time the first N frames of the video, all resident in HBM, "
                          "at batch 1, 4 and 16 (one JSON line)")
-    return ap.parse_args()
+    ap.add_argument("--cpu-probe-rows", type=int, default=0, help=argparse.SUPPRESS)
+    a = ap.parse_args(argv)
+    a.leg_set = set(LEGS) if a.legs == "all" else ({"main"} | set(x for x in a.legs.split(",") if x))
+    unknown = a.leg_set - set(LEGS)
+    if unknown:
+        ap.error(f"unknown legs {sorted(unknown)}")
+    return a
 
 
 def log(msg, quiet=False):
     if not quiet:
         print(msg, file=sys.stderr, flush=True)
+
+
+def frames_to_device(frames: np.ndarray, dtype: str):
+    """[n][H][W][3] storage-dtype array -> contiguous device tensor (bf16 as int16 bits)."""
+    import torch
+    if dtype == "bf16":
+        return torch.from_numpy(np.ascontiguousarray(frames).view(np.int16)).cuda()
+    return torch.from_numpy(np.ascontiguousarray(frames)).cuda()
 
 
 def _render_frame(job):
@@ -94,49 +137,217 @@ def render_video(idx, dtype: str, workers: int = 8) -> np.ndarray:
         return np.concatenate(list(pool.map(_render_frame, [(i, dtype) for i in idx])))
 
 
-def cpu_baseline(target_s: float, levels: int, grid: int, quiet: bool):
-    """Time the FP64 oracle on the benchmark's video frames: a whole-width row
-    band of frame 0 sized for about target_s, or whole frames 0, 1, ... when
-    one frame takes less than that."""
+def _render_config4(dtype):
+    from paper_1706_07263_amd import synth
+    return synth.config4(dtype).frames
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle
+# ---------------------------------------------------------------------------
+
+def _oracle_inputs(levels: int, grid: int, rows: int):
     from oracle import hb_oracle as orc
     from paper_1706_07263_amd import synth
-    from tests import hbtest
-    w = synth.config3((0,))
-    s = dict(w.plan)
-    s["levels"], s["grid_thb"], s["grid_so2"] = levels, grid, grid
-    b = 1 << levels
-    fr = w.frames.astype(np.float64)
-    model = hbtest.oracle_model(synth.spectra())
-    # calibration on a small band, then a band sized for the target time
-    rows = 4 * b
+    sp = synth.spectra()
+    s = synth.plan_settings(levels=levels, grid=grid)
+    params = orc.Params(width=1920, height=rows, levels=levels, grid_thb=grid, grid_so2=grid,
+                        thb_min=s["thb_min"], thb_max=s["thb_max"], so2_min=s["so2_min"], so2_max=s["so2_max"],
+                        lambda_rel=s["lam"], sigma=s["sigma"])
+    model = orc.Model(sp.eps_hb, sp.eps_hbo2, sp.response, sp.path_length_cm)
+    return orc, params, model
+
+
+def cpu_probe(rows: int, levels: int, grid: int) -> None:
+    """Child process: time the oracle on rows 0..rows-1 of video frame 0 with
+    the threads OpenMP gives it (OMP_NUM_THREADS), print one JSON line."""
+    from paper_1706_07263_amd import synth
+    fr = synth.config3((0,)).frames[:, :rows].astype(np.float64)
+    orc, params, model = _oracle_inputs(levels, grid, rows)
     t0 = time.perf_counter()
-    orc.estimate(hbtest.oracle_params(1920, rows, s), model, fr[:, :rows])
+    orc.estimate(params, model, fr)
     dt = time.perf_counter() - t0
+    print(json.dumps({"rows": rows, "seconds": dt, "threads": orc.threads()}), flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(target_s: float, levels: int, grid: int, quiet: bool):
+    """Time the FP64 oracle on the benchmark's video frames on all host
+    threads (a whole-width row band of frame 0 sized for about target_s, or
+    whole frames 0, 1, ... when one frame takes less), and on one thread in a
+    child process (a 16-row band)."""
+    from paper_1706_07263_amd import synth
+    orc, _, model = _oracle_inputs(levels, grid, 8)
+    b = 1 << levels
+    fr = synth.config3((0,)).frames.astype(np.float64)
+
+    def timed(rows, frames):
+        _, params, _ = _oracle_inputs(levels, grid, rows)
+        t0 = time.perf_counter()
+        orc.estimate(params, model, frames[:, :rows])
+        return time.perf_counter() - t0
+
+    rows = 4 * b
+    dt = timed(rows, fr)
     rows = int(min(1080, max(b, rows * target_s / max(dt, 1e-3)))) // b * b
     rows = max(rows, b)
-    t0 = time.perf_counter()
-    orc.estimate(hbtest.oracle_params(1920, rows, s), model, fr[:, :rows])
-    dt = time.perf_counter() - t0
+    dt = timed(rows, fr)
+    lp = (rows // b) * (1920 // b)
     if rows == 1080 and dt < 0.5 * target_s:
-        # a whole frame is quick: time frames 0 .. n-1 together instead
         n = int(min(8, max(2, round(target_s / dt))))
-        fr = render_video(list(range(n)), "f32").astype(np.float64)
-        t0 = time.perf_counter()
-        orc.estimate(hbtest.oracle_params(1920, 1080, s), model, fr)
-        dt = time.perf_counter() - t0
-        log(f"cpu oracle: {n} frames of 1920x1080 in {dt:.2f} s on {orc.threads()} threads", quiet)
-        return {"value": n / dt, "unit": "frames/s", "cores": orc.threads(), "kind": "oracle",
-                "sample": f"frames 0..{n - 1} (1920x1080, {(1080 // b) * (1920 // b)} low-pass pixels x "
-                          f"{grid * grid} nodes each), {dt:.2f} s"}
-    frac = rows / 1080.0
-    log(f"cpu oracle: {rows} rows x 1920 in {dt:.2f} s on {orc.threads()} threads", quiet)
-    return {"value": frac / dt, "unit": "frames/s", "cores": orc.threads(), "kind": "oracle",
-            "sample": f"rows 0..{rows - 1} of frame 0 (1920x{rows} px, "
-                      f"{(rows // b) * (1920 // b)} low-pass pixels x {grid * grid} nodes), "
-                      f"{dt:.2f} s, scaled by {rows}/1080"}
+        frs = render_video(list(range(n)), "f32").astype(np.float64)
+        dt = timed(1080, frs)
+        out = {"value": n / dt, "unit": "frames/s", "cores": orc.threads(), "kind": "oracle",
+               "sample": f"frames 0..{n - 1} (1920x1080, {(1080 // b) * (1920 // b)} low-pass pixels x "
+                         f"{grid * grid} nodes each), {dt:.2f} s"}
+    else:
+        out = {"value": (rows / 1080.0) / dt, "unit": "frames/s", "cores": orc.threads(), "kind": "oracle",
+               "sample": f"rows 0..{rows - 1} of frame 0 (1920x{rows} px, {lp} low-pass pixels x "
+                         f"{grid * grid} nodes), {dt:.2f} s, scaled by {rows}/1080"}
+    log(f"cpu oracle: {out['sample']} on {orc.threads()} threads", quiet)
+    # one thread, in a child process (OpenMP's thread count is fixed at start-up)
+    rows1 = 4 * b
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-probe-rows", str(rows1),
+                        "--levels", str(levels), "--grid", str(grid)], env=env, capture_output=True,
+                       text=True, timeout=600)
+    one = None
+    if r.returncode == 0 and r.stdout.strip():
+        p = json.loads(r.stdout.strip().splitlines()[-1])
+        pairs = (rows1 // b) * (1920 // b) * grid * grid
+        one = {"frames_per_s": (rows1 / 1080.0) / p["seconds"], "threads": p["threads"],
+               "pairs_per_s": pairs / p["seconds"],
+               "sample": f"rows 0..{rows1 - 1} of frame 0, {p['seconds']:.2f} s, scaled by {rows1}/1080"}
+        log(f"cpu oracle, one thread: {one}", quiet)
+    out["cpu_model"] = cpu_model()
+    out["one_thread"] = one
+    return out
 
+
+# ---------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------
 
 PAPER_TABLE1_HZ = {"bayes_full_resolution": 3.54, "proposed_w1": 12.7, "proposed_w3": 14.4, "tikhonov": 43.5}
+
+
+def make_desc(hb, a, W, H, B, dtype=None, **kw):
+    from paper_1706_07263_amd import synth
+    s = synth.plan_settings(levels=kw.pop("levels", a.levels), grid=kw.pop("grid", a.grid))
+    return hb.make_desc(W, H, levels=s["levels"], dtype=dtype or a.dtype, max_batch=B, grid_thb=s["grid_thb"],
+                        grid_so2=s["grid_so2"], lam=s["lam"], sigma=s["sigma"],
+                        grid_split=kw.pop("grid_split", a.split), **kw)
+
+
+def run_timed(hb, torch, plan, frames, maps, stream, steps, warmup):
+    """Warm-up calls, then `steps` calls timed on the host clock between device
+    synchronisations, with the plan's per-kernel HIP events and pair counter.
+    Returns (seconds, stage ms per call, evaluated pairs per posterior launch)."""
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            plan.estimate(frames, maps, stream)
+    torch.cuda.synchronize()
+    hb.hb_plan_set_timing(plan.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            plan.estimate(frames, maps, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms, launches = hb.hb_plan_get_timing(plan.handle)
+    evaluated, full = hb.hb_plan_get_work(plan.handle)
+    hb.hb_plan_set_timing(plan.handle, False)
+    per = ms / np.maximum(launches, 1)
+    return elapsed, per, evaluated / max(launches[1], 1), full / max(launches[1], 1)
+
+
+def time_plan(hb, torch, desc, spectra, frames, maps, stream, steps, warmup):
+    with hb.Plan(desc, 0) as plan:
+        plan.set_forward_model(spectra)
+        elapsed, *_ = run_timed(hb, torch, plan, frames, maps, stream, steps, warmup)
+        return steps * frames.shape[0] / elapsed
+
+
+def posterior_modes(a, hb, torch, synth, frames, maps, stream):
+    """The same frames with exact skipping (tolerance 0: only chunks whose
+    float32 weights are all zero; bit-identical to no skipping) and with no
+    skipping at all (every pair of the grid evaluated)."""
+    B, H, W = frames.shape[0], frames.shape[1], frames.shape[2]
+    out = {}
+    for name, tol, steps in (("exact_skip", 0.0, 6), ("full_grid", -1.0, 3)):
+        with hb.Plan(make_desc(hb, a, W, H, B, posterior_tolerance=tol), 0) as plan:
+            plan.set_forward_model(synth.spectra())
+            elapsed, per, ev, full = run_timed(hb, torch, plan, frames, maps, stream, steps, 1)
+        k2 = per[1] * 1e-3
+        out[name] = {"posterior_tolerance_um": tol, "skip_log2": "none" if tol < 0 else 160,
+                     "frames_per_s": round(steps * B / elapsed, 2), "call_ms": round(per[3], 4),
+                     "posterior_ms": round(per[1], 4), "evaluated_fraction": round(ev / full, 5),
+                     "evaluated_pairs_per_s": ev / k2,
+                     "achieved_tflops": round(ev * FLOPS_PER_PAIR / k2 / 1e12, 3),
+                     "frac_of_ceiling": round(ev / k2 / CEILING_PAIRS_PER_S, 4)}
+        log(f"posterior {name}: {out[name]}", a.quiet)
+    return out
+
+
+def table1_analogue(a, hb, torch, synth, frames, maps, stream):
+    """The paper's speed comparison in kind, on the same frames and grid:
+    posterior on every pixel (levels 0), the proposed method with 1 and 3 Haar
+    levels, and Tikhonov on every coefficient."""
+    B, H, W = frames.shape[0], frames.shape[1], frames.shape[2]
+    modes = {"bayes_full_resolution": dict(levels=0), "proposed_w1": dict(levels=1),
+             "proposed_w3": dict(levels=3), "tikhonov": dict(levels=1, lowpass=hb.HB_LOWPASS_TIKHONOV)}
+    out = {}
+    for name, m in modes.items():
+        desc = make_desc(hb, a, W, H, B, levels=m["levels"], lowpass=m.get("lowpass", hb.HB_LOWPASS_BAYES))
+        steps = 3 if m["levels"] == 0 else 10
+        out[name] = round(time_plan(hb, torch, desc, synth.spectra(), frames, maps, stream, steps, 1), 2)
+        log(f"table 1 analogue: {name} {out[name]} frames/s", a.quiet)
+    base = out["bayes_full_resolution"]
+    pbase = PAPER_TABLE1_HZ["bayes_full_resolution"]
+    return {"frames_per_s": out, "speedup_vs_full_resolution": {k: round(v / base, 2) for k, v in out.items()},
+            "paper_hz": PAPER_TABLE1_HZ,
+            "paper_speedup_vs_full_resolution": {k: round(v / pbase, 2) for k, v in PAPER_TABLE1_HZ.items()},
+            "grid": f"{a.grid}x{a.grid}", "frames": "the benchmark's 1920x1080 frames"}
+
+
+def config4_storage(a, hb, torch, synth, stream):
+    """The stereo 1280x1024 pair with a 512x512 grid and one Haar level, the
+    frames stored in FP32, FP16 and BF16 (each rendered from FP64 with one
+    rounding); both views in one call."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    ctx = multiprocessing.get_context("spawn")
+    dtypes = ("f32", "f16", "bf16")
+    with ProcessPoolExecutor(max_workers=3, mp_context=ctx) as pool:
+        host = dict(zip(dtypes, pool.map(_render_config4, dtypes)))
+    H, W = 1024, 1280
+    maps = [torch.empty((2, H, W), device="cuda", dtype=torch.float32) for _ in range(4)]
+    out = {}
+    for dt in dtypes:
+        fr = frames_to_device(host[dt], dt)
+        with hb.Plan(make_desc(hb, a, W, H, 2, dtype=dt, levels=1, grid=512, grid_split=0), 0) as plan:
+            plan.set_forward_model(synth.spectra())
+            elapsed, per, ev, full = run_timed(hb, torch, plan, fr, maps, stream, 10, 2)
+        out[dt] = {"frames_per_s": round(20 / elapsed, 2), "call_ms": round(per[3], 4),
+                   "log_haar_ms": round(per[0], 4), "posterior_ms": round(per[1], 4),
+                   "evaluated_fraction": round(ev / full, 5)}
+        del fr
+    for dt in ("f16", "bf16"):
+        out[dt]["vs_f32"] = round(out[dt]["frames_per_s"] / out["f32"]["frames_per_s"], 4)
+    out["workload"] = "stereo pair 1280x1024 (2 frames per call), 1 Haar level, 512x512 grid"
+    log(f"config 4 storage: {out}", a.quiet)
+    return out
 
 
 def host_serial(torch, plan, host, dev, maps, stream, steps, warmup) -> float:
@@ -183,74 +394,56 @@ def host_overlapped(torch, plan, host, dev, maps, stream, steps, warmup) -> floa
     return steps / (time.perf_counter() - t0)
 
 
-def time_plan(hb, torch, desc, spectra, frames, maps, stream, steps, warmup):
-    with hb.Plan(desc, 0) as plan:
-        plan.set_forward_model(spectra)
-        with torch.cuda.stream(stream):
-            for _ in range(warmup):
-                plan.estimate(frames, maps, stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        with torch.cuda.stream(stream):
-            for _ in range(steps):
-                plan.estimate(frames, maps, stream)
-        torch.cuda.synchronize()
-        return steps * frames.shape[0] / (time.perf_counter() - t0)
-
-
-def table1_analogue(a, hb, torch, synth, frames, maps, stream, settings):
-    """The paper's speed comparison in kind, on the same frames and grid:
-    posterior on every pixel (levels 0), the proposed method with 1 and 3 Haar
-    levels, and Tikhonov on every coefficient."""
-    H, W = frames.shape[1], frames.shape[2]
-    modes = {"bayes_full_resolution": dict(levels=0), "proposed_w1": dict(levels=1),
-             "proposed_w3": dict(levels=3), "tikhonov": dict(levels=1, lowpass=hb.HB_LOWPASS_TIKHONOV)}
-    out = {}
-    for name, m in modes.items():
-        desc = hb.make_desc(W, H, levels=m["levels"], dtype=a.dtype, max_batch=frames.shape[0], grid_thb=a.grid,
-                            grid_so2=a.grid, lam=settings["lam"], sigma=settings["sigma"],
-                            lowpass=m.get("lowpass", hb.HB_LOWPASS_BAYES))
-        steps = 3 if m["levels"] == 0 else 10
-        out[name] = round(time_plan(hb, torch, desc, synth.spectra(), frames, maps, stream, steps, 1), 2)
-        log(f"table 1 analogue: {name} {out[name]} frames/s", a.quiet)
-    base = out["bayes_full_resolution"]
-    pbase = PAPER_TABLE1_HZ["bayes_full_resolution"]
-    return {"frames_per_s": out, "speedup_vs_full_resolution": {k: round(v / base, 2) for k, v in out.items()},
-            "paper_hz": PAPER_TABLE1_HZ,
-            "paper_speedup_vs_full_resolution": {k: round(v / pbase, 2) for k, v in PAPER_TABLE1_HZ.items()},
-            "grid": f"{a.grid}x{a.grid}", "frames": "the benchmark's 1920x1080 frames"}
-
-
 SERVE_MAX_BATCH = {(480, 640): 8, (1024, 1280): 6, (1080, 1920): 4, (2160, 3840): 2}
 
 
 def serving(a):
-    """16 Poisson camera streams of mixed resolution at 30 fps, FP16 frames."""
+    """16 Poisson camera streams of mixed resolution, FP16 frames: at 30
+    frames/s per stream, then at a rate scaled so that the lanes are busy
+    about a.serve_target_busy of the time (one calibration run, then the
+    measured run), with a.serve_sources distinct frames per class."""
     import torch
     from paper_1706_07263_amd import synth
     from paper_1706_07263_amd.serve import GpuExecutor, Server, render_sources, workload_requests
-    reqs, offered = workload_requests(a.serve_warmup + a.serve_seconds)
+    dur = a.serve_warmup + a.serve_seconds
+    _, offered = workload_requests(dur, n_sources=a.serve_sources)
     classes = sorted(offered, key=lambda c: c.pixels)
-    log(f"serving: rendering {len(classes)} source frames", a.quiet)
-    raw = render_sources(classes, n_sources=1, workers=8)
+    log(f"serving: rendering {len(classes)} x {a.serve_sources} source frames", a.quiet)
+    raw = render_sources(classes, n_sources=a.serve_sources, workers=8)
     sources = {c: torch.from_numpy(v).pin_memory() for c, v in raw.items()}
     ex = GpuExecutor(synth.spectra(), sources)
     srv = Server(ex, {c: SERVE_MAX_BATCH[(c.height, c.width)] for c in classes},
                  hbm_budget=int(a.serve_budget_gib * (1 << 30)), offered=offered, max_lanes=2)
-    log(f"serving: {len(srv.lanes)} lanes, {srv.used / 2**30:.2f} GiB; {len(reqs)} frames over "
-        f"{a.serve_warmup + a.serve_seconds:.1f} s", a.quiet)
-    rep = srv.run(reqs, warmup_s=a.serve_warmup)
+    log(f"serving: {len(srv.lanes)} lanes, {srv.used / 2**30:.2f} GiB", a.quiet)
+
+    def point(fps, duration, warmup):
+        reqs, off = workload_requests(duration, fps=fps, n_sources=a.serve_sources)
+        rep = srv.run(reqs, warmup_s=warmup)
+        out = rep.summary()
+        out["fps_per_stream"] = round(fps, 2)
+        out["offered_pairs_per_s"] = sum(off.values())
+        out["offered_mpixel_per_s"] = round(sum(r.cls.pixels for r in reqs) / duration / 1e6, 1)
+        out["window_s"] = round(duration - warmup, 3)
+        out["sources_per_class"] = a.serve_sources
+        log(f"serving at {fps:.1f} frames/s per stream: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, "
+            f"{out['mpixel_per_s']} Mpixel/s, busy {out['lane_busy_fraction']}, mean batch {out['mean_batch']}",
+            a.quiet)
+        return out
+
+    base = point(30.0, dur, a.serve_warmup)
+    base["streams"] = 16
+    # loaded point: scale the rate from a short calibration run
+    busy = max(base["lane_busy_fraction"], 1e-3)
+    fps = 30.0 * a.serve_target_busy / busy
+    cal = point(fps, 3.0, 1.0)
+    fps *= a.serve_target_busy / max(cal["lane_busy_fraction"], 1e-3)
+    loaded = point(fps, dur, a.serve_warmup)
+    loaded["calibration"] = {"fps_per_stream": cal["fps_per_stream"], "lane_busy_fraction": cal["lane_busy_fraction"]}
     srv.close()
-    out = rep.summary()
-    out["streams"] = 16
-    out["offered_pairs_per_s"] = sum(offered.values())
-    out["offered_mpixel_per_s"] = round(sum(r.cls.pixels for r in reqs) / (a.serve_warmup + a.serve_seconds) / 1e6, 1)
-    out["window_s"] = a.serve_seconds
-    log(f"serving: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, {out['mpixel_per_s']} Mpixel/s", a.quiet)
-    return out
+    return base, loaded
 
 
-def sequence(a, torch, hb, synth, hbtest):
+def sequence(a, torch, hb, synth):
     """Frames 0..N-1 of the 1920x1080 video rendered once and kept in HBM,
     then estimated in order at batch 1, 4 and 16 (the last call of a pass
     takes what is left), each pass timed on the host clock between device
@@ -260,17 +453,14 @@ def sequence(a, torch, hb, synth, hbtest):
     parts = []
     for s0 in range(0, n, 32):
         idx = list(range(s0, min(n, s0 + 32)))
-        parts.append(hbtest.to_device(render_video(idx, a.dtype, workers=16), a.dtype))
+        parts.append(frames_to_device(render_video(idx, a.dtype, workers=16), a.dtype))
         log(f"rendered frames {idx[0]}..{idx[-1]}", a.quiet)
     frames = torch.cat(parts)
     del parts
-    settings = dict(synth.config3((0,), dtype=a.dtype).plan)
     fps, mpx = {}, {}
     for B in (1, 4, 16):
         maps = [torch.empty((B, H, W), device=dev, dtype=torch.float32) for _ in range(4)]
-        desc = hb.make_desc(W, H, levels=a.levels, dtype=a.dtype, max_batch=B, grid_thb=a.grid,
-                            grid_so2=a.grid, lam=settings["lam"], sigma=settings["sigma"], grid_split=a.split)
-        with hb.Plan(desc, 0) as plan:
+        with hb.Plan(make_desc(hb, a, W, H, B), 0) as plan:
             plan.set_forward_model(synth.spectra())
             stream = torch.cuda.Stream(dev)
             with torch.cuda.stream(stream):
@@ -294,6 +484,9 @@ def sequence(a, torch, hb, synth, hbtest):
 
 def main():
     a = parse()
+    if a.cpu_probe_rows:
+        cpu_probe(a.cpu_probe_rows, a.levels, a.grid)
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported "
               "(each frame and each stream is independent: see the sharding notes)", file=sys.stderr)
@@ -313,68 +506,56 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     from paper_1706_07263_amd import hb, synth
-    from tests import hbtest
     if a.sequence:
-        sequence(a, torch, hb, synth, hbtest)
+        sequence(a, torch, hb, synth)
         return
+    legs = a.leg_set
 
     B = a.batch
     H, W = 1080, 1920
     log(f"generating {B} synthetic 1080p frames", a.quiet)
     idx = [int(i * 300 / B) for i in range(B)]
-    wl = synth.config3((0,), dtype=a.dtype)
-    wl.frames = render_video(idx, a.dtype)
-    settings = dict(wl.plan)
-    settings["levels"], settings["grid_thb"], settings["grid_so2"] = a.levels, a.grid, a.grid
-
     dev = torch.device("cuda:0")
-    frames = hbtest.to_device(wl.frames, a.dtype)
+    frames = frames_to_device(render_video(idx, a.dtype), a.dtype)
     maps = [torch.empty((B, H, W), device=dev, dtype=torch.float32) for _ in range(4)]
-    desc = hb.make_desc(W, H, levels=a.levels, dtype=a.dtype, max_batch=B, grid_thb=a.grid,
-                        grid_so2=a.grid, lam=settings["lam"], sigma=settings["sigma"], grid_split=a.split)
-    plan = hb.Plan(desc, 0).set_forward_model(synth.spectra())
+    plan = hb.Plan(make_desc(hb, a, W, H, B), 0).set_forward_model(synth.spectra())
     info = plan.info()
     stream = torch.cuda.Stream(dev)
 
-    log(f"warmup {a.warmup}", a.quiet)
-    with torch.cuda.stream(stream):
-        for _ in range(a.warmup):
-            plan.estimate(frames, maps, stream)
-    torch.cuda.synchronize()
-
-    hb.hb_plan_set_timing(plan.handle, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for _ in range(a.steps):
-            plan.estimate(frames, maps, stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms, launches = hb.hb_plan_get_timing(plan.handle)
-    evaluated, full = hb.hb_plan_get_work(plan.handle)
-    hb.hb_plan_set_timing(plan.handle, False)
-    log(f"timed {a.steps} steps in {elapsed:.3f} s; stage ms {ms / np.maximum(launches, 1)}", a.quiet)
+    log(f"warmup {a.warmup}, timed {a.steps}", a.quiet)
+    elapsed, per, eval_per_launch, full_per_launch = run_timed(hb, torch, plan, frames, maps, stream,
+                                                               a.steps, a.warmup)
+    plan.close()
+    log(f"timed {a.steps} steps in {elapsed:.3f} s; stage ms {per}", a.quiet)
 
     fps = a.steps * B / elapsed
     LL = (H >> a.levels) * (W >> a.levels)
-    pairs_per_launch = B * LL * a.grid * a.grid
-    k2_s = ms[1] / max(launches[1], 1) / 1e3
-    # Evaluated pairs per launch (chunks whose weights are exactly zero are
-    # skipped; the flops of the roofline are those actually executed).
-    eval_per_launch = evaluated / max(launches[1], 1) if evaluated else pairs_per_launch
+    k2_s = per[1] / 1e3
+    eval_rate = eval_per_launch / k2_s
     achieved = eval_per_launch * FLOPS_PER_PAIR / k2_s / 1e12
     sha = kernel_source_sha()
     default_workload = (B, a.levels, a.grid, a.dtype, a.split) == (16, 2, 256, "f32", 0)
     traffic = PROFILED_POSTERIOR_TRAFFIC if (sha == PROFILED_KERNEL_SHA and default_workload) else None
-    roofline = {"bound": "alu", "kernel": "k_posterior", "achieved": round(achieved, 3),
-                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": traffic, "traffic_unit": "bytes per launch", "avg_launch_ms": round(k2_s * 1e3, 4),
-                "evaluated_pairs_per_launch": int(eval_per_launch), "full_grid_pairs_per_launch": pairs_per_launch,
-                "evaluated_pairs_per_s": eval_per_launch / k2_s,
-                "full_grid_pairs_per_s": pairs_per_launch / k2_s,
-                "flops_per_pair": FLOPS_PER_PAIR, "exps_per_pair": EXPS_PER_PAIR}
-    stage = {"log_haar_ms": ms[0] / max(launches[0], 1), "posterior_ms": ms[1] / max(launches[1], 1),
-             "recompose_ms": ms[2] / max(launches[2], 1), "call_ms": ms[3] / max(launches[3], 1)}
+    roofline = {
+        "bound": "alu", "kernel": "k_posterior", "achieved": round(achieved, 3), "peak": round(CEILING_TFLOPS, 2),
+        "unit": "TFLOP/s", "frac": round(achieved / CEILING_TFLOPS, 4), "traffic": traffic,
+        "traffic_unit": "bytes per launch",
+        "peak_basis": f"issue ceiling of the posterior's chunk evaluation: {CHUNK_BLOCK_CYCLES} SIMD cycles per "
+                      f"256 pairs (1 bf16 16x16x32 MFMA = {MFMA_CYCLES}, 4 v_exp_f32 x {EXP_CYCLES}, "
+                      f"9 FP32 VALU x {FMA_CYCLES}) on {N_SIMD} SIMDs at {CLOCK_HZ / 1e9} GHz = "
+                      f"{CEILING_PAIRS_PER_S:.3e} pairs/s x {FLOPS_PER_PAIR} flops",
+        "unit_of_work": "evaluated (low-pass pixel, grid node) pair; skipped chunks are not counted",
+        "avg_launch_ms": round(per[1], 4), "launches_timed": a.steps,
+        "evaluated_pairs_per_launch": int(eval_per_launch), "full_grid_pairs_per_launch": int(full_per_launch),
+        "evaluated_fraction": round(eval_per_launch / max(full_per_launch, 1), 5),
+        "evaluated_pairs_per_s": eval_rate, "ceiling_pairs_per_s": CEILING_PAIRS_PER_S,
+        "full_grid_pairs_per_s_equivalent": full_per_launch / k2_s,
+        "flops_per_pair": FLOPS_PER_PAIR, "flops_per_pair_on_mfma": FLOPS_PER_PAIR_MFMA,
+        "flops_per_pair_on_valu": FLOPS_PER_PAIR_VALU, "exps_per_pair": EXPS_PER_PAIR,
+        "frac_of_fp32_vector_peak": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+        "frac_of_unpacked_fp32_peak": round(achieved / FP32_UNPACKED_PEAK_TFLOPS, 4),
+    }
+    stage = {"log_haar_ms": per[0], "posterior_ms": per[1], "recompose_ms": per[2], "call_ms": per[3]}
     # K1 algorithmic bytes: frames read; detail part (8 B/px) and the
     # double-float low-pass observation (24 B per low-pass pixel) written.
     k1_bytes = B * H * W * ((12 if a.dtype == "f32" else 6) + 8) + B * LL * 24
@@ -384,43 +565,45 @@ def main():
     stage["recompose_fused"] = bool(info["grid_split"] == 1 and info["posterior_kernel"] == "mfma"
                                     and a.levels <= 2)
 
-    plan.close()
+    ceil = None
+    if "ceiling" in legs:
+        from paper_1706_07263_amd import ceiling
+        ceil = ceiling.ceilings(6)
+        roofline["measured_mix_ceiling_pairs_per_s"] = ceil["mix_pairs_per_s"]
+        roofline["frac_of_measured_mix_ceiling"] = round(eval_rate / ceil["mix_pairs_per_s"], 4)
+        log(f"ceilings: {ceil}", a.quiet)
 
-    table1 = None if a.no_table1 else table1_analogue(a, hb, torch, synth, frames, maps, stream, settings)
+    modes = None
+    if "modes" in legs:
+        modes = posterior_modes(a, hb, torch, synth, frames, maps, stream)
+        modes["default"] = {"posterior_tolerance_um": 1e-6, "skip_log2": info["skip_log2"],
+                            "skip_bound_um": info["skip_bound"], "frames_per_s": round(fps, 2),
+                            "call_ms": round(per[3], 4), "posterior_ms": round(per[1], 4),
+                            "evaluated_fraction": roofline["evaluated_fraction"],
+                            "evaluated_pairs_per_s": eval_rate, "achieved_tflops": round(achieved, 3),
+                            "frac_of_ceiling": round(eval_rate / CEILING_PAIRS_PER_S, 4)}
 
-    # The same frames stored in FP16 (device-side RNE cast), same plan settings.
+    table1 = table1_analogue(a, hb, torch, synth, frames, maps, stream) if "table1" in legs else None
+
     half = None
-    if a.dtype == "f32":
+    if "fp16" in legs and a.dtype == "f32":
         frames16 = frames.half()
-        desc16 = hb.make_desc(W, H, levels=a.levels, dtype="f16", max_batch=B, grid_thb=a.grid,
-                              grid_so2=a.grid, lam=settings["lam"], sigma=settings["sigma"], grid_split=a.split)
-        with hb.Plan(desc16, 0) as plan16:
+        with hb.Plan(make_desc(hb, a, W, H, B, dtype="f16"), 0) as plan16:
             plan16.set_forward_model(synth.spectra())
-            with torch.cuda.stream(stream):
-                for _ in range(a.warmup):
-                    plan16.estimate(frames16, maps, stream)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            with torch.cuda.stream(stream):
-                for _ in range(a.steps):
-                    plan16.estimate(frames16, maps, stream)
-            torch.cuda.synchronize()
-            fps16 = a.steps * B / (time.perf_counter() - t1)
+            e16, *_ = run_timed(hb, torch, plan16, frames16, maps, stream, a.steps, a.warmup)
+        fps16 = a.steps * B / e16
         half = {"frames_per_s": round(fps16, 3), "vs_fp32": round(fps16 / fps, 4)}
         log(f"fp16 storage: {fps16:.1f} frames/s", a.quiet)
         del frames16
+
     # End to end with the frames copied from pinned host memory every step
-    # (the library takes device pointers, so this is context, not the value):
-    # serially on one stream, and overlapped (a copy stream fills one of two
-    # device slots while the other is estimated), for FP32 and FP16 storage.
+    # (the library takes device pointers, so this is context, not the value).
     pcie = None
-    if not a.no_table1 and a.dtype == "f32":
+    if "pcie" in legs and a.dtype == "f32":
         pcie = {"host_bytes_per_frame_f32": H * W * 12, "host_bytes_per_frame_f16": H * W * 6}
         for tag, dev_frames, dt in (("f32", frames, "f32"), ("f16", frames.half(), "f16")):
             host = dev_frames.cpu().pin_memory()
-            d_h = hb.make_desc(W, H, levels=a.levels, dtype=dt, max_batch=B, grid_thb=a.grid, grid_so2=a.grid,
-                               lam=settings["lam"], sigma=settings["sigma"], grid_split=a.split)
-            with hb.Plan(d_h, 0) as plan_h:
+            with hb.Plan(make_desc(hb, a, W, H, B, dtype=dt), 0) as plan_h:
                 plan_h.set_forward_model(synth.spectra())
                 if tag == "f32":
                     pcie["serial_frames_per_s_f32"] = round(
@@ -430,25 +613,29 @@ def main():
             del host
         log(f"frames from pinned host memory (frames/s): {pcie}", a.quiet)
 
-    # Throughput at the batch sizes of the video workload (the first b of the
-    # frames above, one plan per batch size).
-    sweep = {}
-    if not a.no_table1:
+    sweep = None
+    if "sweep" in legs:
+        sweep = {}
         for b in (1, 4, 8, 16):
             if b > B:
                 continue
-            d = hb.make_desc(W, H, levels=a.levels, dtype=a.dtype, max_batch=b, grid_thb=a.grid,
-                             grid_so2=a.grid, lam=settings["lam"], sigma=settings["sigma"])
             sub = frames[:b]
             subm = [m[:b] for m in maps]
-            sweep[str(b)] = round(time_plan(hb, torch, d, synth.spectra(), sub, subm, stream, a.steps, a.warmup), 2)
+            sweep[str(b)] = round(time_plan(hb, torch, make_desc(hb, a, W, H, b), synth.spectra(), sub, subm,
+                                            stream, a.steps, a.warmup), 2)
         log(f"batch sweep (frames/s): {sweep}", a.quiet)
     del frames, maps
     torch.cuda.empty_cache()
-    serve = serving(a) if a.serve_seconds > 0 else None
+
+    c4 = config4_storage(a, hb, torch, synth, stream) if "config4" in legs else None
+    torch.cuda.empty_cache()
+
+    serve = serve_load = None
+    if "serve" in legs and a.serve_seconds > 0:
+        serve, serve_load = serving(a)
 
     cpu = None
-    if a.cpu_seconds > 0:
+    if "cpu" in legs and a.cpu_seconds > 0:
         cpu = cpu_baseline(a.cpu_seconds, a.levels, a.grid, a.quiet)
 
     out = {
@@ -460,17 +647,24 @@ def main():
                                f"THb x SO2 posterior grid, {a.dtype} frames",
                    "global_batch": B, "frame": "1920x1080", "levels": a.levels,
                    "grid": f"{a.grid}x{a.grid}", "grid_split": info["grid_split"],
-                   "posterior_kernel": info["posterior_kernel"], "parallelism": "1 GPU"},
+                   "posterior_kernel": info["posterior_kernel"],
+                   "posterior_tolerance_um": 1e-6, "skip_log2": info["skip_log2"],
+                   "parallelism": "1 GPU"},
         "mpixel_per_s": round(fps * H * W / 1e6, 2),
-        "stages_ms_per_call": {k: round(v, 4) for k, v in stage.items()},
+        "stages_ms_per_call": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stage.items()},
         "roofline": roofline,
-        "batch_sweep_frames_per_s": sweep or None,
+        "posterior_modes": modes,
+        "ceiling": ceil,
+        "batch_sweep_frames_per_s": sweep,
         "pinned_host_input": pcie,
         "fp16_storage": half,
+        "config4_storage": c4,
         "table1_analogue": table1,
         "cpu_baseline": cpu,
         "p99_latency_ms_16_streams": serve["p99_ms"] if serve else None,
         "serving": serve,
+        "serving_loaded": serve_load,
+        "kernel_source_sha": sha,
     }
     print(json.dumps(out), flush=True)
 
