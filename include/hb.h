@@ -125,6 +125,8 @@ typedef struct {
     double skip_log2;     /* T: chunks whose logit bound lies more than T below the reference are skipped
                              (+inf: nothing is skipped)                                                   */
     double skip_bound;    /* uM, the stated bound on the posterior-mean change from skipping (0: exact)  */
+    double mfma_index;    /* R^2 h: squared super-tile radius (scaled log-attenuation units) times the
+                             node spacing (uM).  The MFMA kernel runs when it is <= 700                   */
 } hb_plan_info_t;
 
 /* Fill `desc` with defaults: 64x64, 1 level, FP32, max_batch 1, grid 128x128

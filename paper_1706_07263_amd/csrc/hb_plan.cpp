@@ -574,7 +574,8 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
     p->radius = build_supers(d, model, r, (double)p->scale, p->side, tiles);
     const double h_thb = d.grid_thb > 1 ? (d.thb_max - d.thb_min) / (d.grid_thb - 1) : 0.0;
     const double h_so2 = d.grid_so2 > 1 ? d.thb_max * (d.so2_max - d.so2_min) / (d.grid_so2 - 1) : 0.0;
-    p->use_mfma = p->radius * p->radius * std::max(h_thb, h_so2) <= kMfmaPrecisionBudget;
+    p->info.mfma_index = p->radius * p->radius * std::max(h_thb, h_so2);
+    p->use_mfma = p->info.mfma_index <= kMfmaPrecisionBudget;
     p->info.posterior_kernel = p->use_mfma ? 0 : 1;
     // Exact skipping (T = kExactSkipLog2) has no error.
     p->info.skip_bound = (p->skip_log2 < kExactSkipLog2)

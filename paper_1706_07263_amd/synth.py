@@ -63,6 +63,22 @@ def spectra() -> Spectra:
                    PATH_LENGTH_CM)
 
 
+# Other cameras for tests of the forward-model handling: the same extinction
+# curves with different channel responses and path length.
+#   "shifted": responses moved by 20 nm (R 630, G 520, B 480 nm) and a 0.2 cm
+#              path (cond(E) 10.6 at the grid centre, |M|_inf 1.4e3);
+#   "narrow":  responses 600/560/520 nm, 0.2 cm (closely spaced channels,
+#              cond(E) 14.8, |M|_inf 1.4e3).
+ALT_CAMERAS = {"shifted": ((630.0, 520.0, 480.0), 0.2), "narrow": ((600.0, 560.0, 520.0), 0.2)}
+
+
+def alt_spectra(name: str) -> Spectra:
+    centres, path = ALT_CAMERAS[name]
+    wl = WAVELENGTHS_NM.copy()
+    resp = np.stack([_gauss_sum(wl, ((1.0, c, 30.0),)) for c in centres])
+    return Spectra(wl, _gauss_sum(wl, EPS_HB_TERMS), _gauss_sum(wl, EPS_HBO2_TERMS), resp, path)
+
+
 # ----------------------------------------------------------------------------
 # Ground-truth fields: sums of Gaussian blobs, analytic so they can be sampled
 # at moved coordinates.
