@@ -46,8 +46,13 @@ typedef enum {
     HB_ERR_OUT_OF_MEMORY = -4,    /* device allocation failed                    */
     HB_ERR_DEVICE = -5,           /* a HIP call or kernel launch failed          */
     HB_ERR_ILL_POSED = -6,        /* E'E + gamma I is singular                   */
-    HB_ERR_BATCH = -7             /* n_frames > max_batch                        */
+    HB_ERR_BATCH = -7,            /* n_frames > max_batch                        */
+    HB_ERR_SCRATCH = -8           /* hb_estimate_frames_noalloc: the call's
+                                     buffers exceed HB_NOALLOC_SCRATCH_BYTES     */
 } hb_status_t;
+
+/* Size of the static per-device scratch array of hb_estimate_frames_noalloc. */
+#define HB_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
 
 typedef enum { HB_F32 = 0, HB_F16 = 1, HB_BF16 = 2 } hb_dtype_t;
 
@@ -150,6 +155,27 @@ hb_status_t hb_set_forward_model(hb_plan_t plan, const hb_forward_model_t *fm);
  * so it may be captured into a HIP graph.  n_frames == 0 is a no-op. */
 hb_status_t hb_estimate_frames(hb_plan_t plan, const void *d_frames, int32_t n_frames,
                                const hb_maps_t *d_out, void *stream);
+
+/* hb_estimate_frames for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, bit for bit, but the call's
+ * intermediate buffers live in a static device array of
+ * HB_NOALLOC_SCRATCH_BYTES that the library holds on each device until the
+ * process ends (set up by hb_plan_create), instead of the plan's own scratch.
+ * The call allocates and frees nothing.  Arguments, ownership and errors are
+ * those of hb_estimate_frames, plus HB_ERR_SCRATCH (nothing launched) when
+ * n_frames frames need more than the array: per frame, 24 B per low-pass
+ * pixel (observation) + 8 B per pixel (detail part) + 24 B x grid_split per
+ * low-pass pixel (posterior partials, Bayesian low-pass only) + 4 B per
+ * low-pass pixel (split grids only) + 8 B per low-pass pixel (estimate), each
+ * buffer rounded up to 256 B (one 1920x1080 frame at 2 levels and one split:
+ * 23.8 MB; one 3840x2160 frame at 2 levels: 95 MB).  Every call on a device
+ * shares that device's array and leaves its contents there: calls of this
+ * function that overlap in time on one device (different streams, plans or
+ * host threads) race and give wrong results; calls ordered on one stream do
+ * not.  hb_debug_copy shows the buffers of hb_estimate_frames calls only. */
+hb_status_t hb_estimate_frames_noalloc(hb_plan_t plan, const void *d_frames, int32_t n_frames,
+                                       const hb_maps_t *d_out, void *stream);
 
 /* Wait for the plan's last hb_estimate_frames call (not for other streams, and
  * not for replays of graphs the caller captured: those are the caller's to wait

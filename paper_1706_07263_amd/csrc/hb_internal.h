@@ -174,6 +174,15 @@ struct RecomposeArgs {
     float *hb, *hbo2, *thb, *so2;
 };
 
+// Static scratch of hb_estimate_frames_noalloc (hb_kernels.hip): one device
+// array of kStaticScratchBytes per device.  static_scratch() must be called
+// with `device` current; it looks the array's device address up once per
+// device (at plan creation, so that the allocation-free call never loads
+// modules or looks up symbols) and returns it.
+constexpr size_t kStaticScratchBytes = HB_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxScratchDevices = 64;
+hipError_t static_scratch(int device, void **ptr);
+
 // Launchers (hb_kernels.hip).  They only enqueue work.
 hipError_t launch_tikhonov_fp64(const double *d_in, double *d_out, float *d_mf, hipStream_t s);
 hipError_t launch_log_haar(const void *frames, int n_frames, const HaarArgs &a, hipStream_t s);

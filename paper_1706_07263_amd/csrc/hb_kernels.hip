@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 
 #include "hb_df.h"
@@ -1476,6 +1477,35 @@ hipError_t launch_recompose(int n_frames, const RecomposeArgs &a, hipStream_t s)
     else
         hipLaunchKernelGGL(k_recompose<1>, dim3((unsigned)blocks), dim3(kBlockThreads), 0, s, b);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of hb_estimate_frames_noalloc: the per-call buffers
+// (low-pass observation, detail part, posterior partials, global reference,
+// low-pass estimate) are carved out of this array instead of the plan's own
+// allocations.  Each device holds its own copy for the life of the process.
+// Host code never passes the array's name to a kernel (on the host it is only
+// a registration handle): static_scratch() looks up the device address once
+// per device, with that device current, and every launch uses that address.
+// ---------------------------------------------------------------------------
+namespace {
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(int device, void **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 }  // namespace hb

@@ -46,6 +46,7 @@ struct hb_plan_s {
     float *d_gref = nullptr;  // global posterior reference per LL pixel (split grids)
     float2 *d_est = nullptr;
     unsigned long long *d_work = nullptr;  // posterior pairs evaluated while timing
+    void *scratch = nullptr;  // device address of the static scratch array (hb_estimate_frames_noalloc)
     size_t bytes = 0;
     long long full_pairs = 0;              // algorithmic pairs of the timed calls
 
@@ -378,6 +379,152 @@ void build_split_ops(const std::vector<float> &table, int n_sup, int side, std::
         }
 }
 
+// Per-call device buffers of hb_estimate_frames: the plan's own, or carved
+// from the static scratch array by hb_estimate_frames_noalloc.
+struct CallBuffers {
+    float *z;       // [n][6][LL] low-pass observation
+    float2 *det;    // [n][H][W] detail part
+    float *part;    // [n][split][kPartFields][LL] posterior partials (Bayesian low-pass)
+    float *gref;    // [n][LL] global posterior reference (split grids), else null
+    float2 *est;    // [n][LL] low-pass estimate
+};
+
+// Argument and state checks shared by both estimate calls (nothing launched).
+hb_status_t check_call(hb_plan_t p, const void *d_frames, int32_t n_frames, const hb_maps_t *d_out) {
+    if (!p || !d_out) return HB_ERR_INVALID_ARG;
+    if (n_frames < 0) return HB_ERR_INVALID_ARG;
+    if (n_frames > p->desc.max_batch) return HB_ERR_BATCH;
+    if (!p->has_model) return HB_ERR_NO_FORWARD_MODEL;
+    if (n_frames == 0) return HB_OK;
+    if (!d_frames) return HB_ERR_INVALID_ARG;
+    return HB_OK;
+}
+
+// Lay the buffers of an n-frame call out in the static scratch (each rounded
+// up to 256 bytes); false if they do not fit.
+bool carve_scratch(const hb_plan_s *p, int n, unsigned char *base, CallBuffers &cb) {
+    const size_t LL = (size_t)p->dims.LL, HW = (size_t)p->desc.width * p->desc.height, nb = (size_t)n;
+    const bool bayes = p->desc.lowpass == HB_LOWPASS_BAYES;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *q = base + off;
+        off += (bytes + 255) / 256 * 256;
+        return q;
+    };
+    cb.z = (float *)take(sizeof(float) * nb * 6 * LL);
+    cb.det = (float2 *)take(sizeof(float2) * nb * HW);
+    cb.part = bayes ? (float *)take(sizeof(float) * nb * p->split * kPartFields * LL) : nullptr;
+    cb.gref = (bayes && p->split > 1) ? (float *)take(sizeof(float) * nb * LL) : nullptr;
+    cb.est = (float2 *)take(sizeof(float2) * nb * LL);
+    return off <= kStaticScratchBytes;
+}
+
+// The launch sequence of one estimate call into the buffers cb (arguments
+// already checked).  `timed`: record the plan's timing events and work
+// counter when timing is enabled (hb_estimate_frames_noalloc passes false:
+// creating events could allocate).
+hb_status_t estimate(hb_plan_s *p, const void *d_frames, int32_t n_frames, const hb_maps_t *d_out, hipStream_t s,
+                     const CallBuffers &cb, bool timed) {
+    if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
+    hipEvent_t *ev = nullptr;
+    if (timed && p->timing && p->timed_calls < kMaxTimedCalls) {
+        const size_t need = 4 * (size_t)(p->timed_calls + 1);
+        while (p->events.size() < need) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return HB_ERR_DEVICE;
+            p->events.push_back(e);
+        }
+        ev = &p->events[4 * (size_t)p->timed_calls];
+        p->timed_calls++;
+    }
+    auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
+
+    HaarArgs ha{};
+    ha.d = p->dims;
+    ha.dtype = p->desc.frame_dtype;
+    ha.floor = (float)p->desc.intensity_floor;
+    for (int k = 0; k < 3; ++k) ha.iref[k] = p->iref[k];
+    ha.M = p->d_mf;
+    ha.z = cb.z;
+    ha.det = cb.det;
+    ha.project = p->desc.illumination && p->desc.lowpass == HB_LOWPASS_BAYES;
+
+    if (mark(0) != hipSuccess) return HB_ERR_DEVICE;
+    if (launch_log_haar(d_frames, n_frames, ha, s) != hipSuccess) return HB_ERR_DEVICE;
+    if (mark(1) != hipSuccess) return HB_ERR_DEVICE;
+    bool fused = false;
+    if (p->desc.lowpass == HB_LOWPASS_BAYES) {
+        PosteriorArgs pa{};
+        pa.LL = p->dims.LL;
+        pa.hl = p->dims.hl;
+        pa.wl = p->dims.wl;
+        pa.n_frames = n_frames;
+        pa.z = cb.z;
+        pa.supers = p->d_tiles;
+        pa.split_ops = p->d_split;
+        pa.n_supers = p->n_tiles;
+        pa.super_stride = super_floats(p->side);
+        pa.chunks_per_super = (p->side / 4) * (p->side / 4);
+        pa.split = p->split;
+        pa.scale = p->scale;
+        pa.skip_log2 = p->skip_log2;
+        pa.part = cb.part;
+        pa.work = ev ? p->d_work : nullptr;
+        if (ev) p->full_pairs += (long long)n_frames * p->dims.LL * p->n_nodes;
+        if (cb.gref) {
+            pa.gref = cb.gref;
+            if (launch_reference(pa, s) != hipSuccess) return HB_ERR_DEVICE;
+        }
+        // One split, MFMA kernel, n <= 2: the posterior writes the maps.
+        fused = p->use_mfma && p->split == 1 && p->dims.levels <= 2;
+        if (fused) {
+            const int B = 1 << p->dims.levels;
+            auto fits = [&](int v) {
+                if (B % v) return false;
+                for (const float *m : {d_out->hb, d_out->hbo2, d_out->thb, d_out->so2})
+                    if (m && ((uintptr_t)m % (sizeof(float) * v)) != 0) return false;
+                return true;
+            };
+            pa.fuse = 1;
+            pa.vec = fits(4) ? 4 : (fits(2) ? 2 : 1);
+            pa.levels = p->dims.levels;
+            pa.H = p->dims.H;
+            pa.W = p->dims.W;
+            pa.det = cb.det;
+            pa.est = cb.est;
+            pa.thb_eps = (float)p->desc.thb_eps;
+            pa.hb = d_out->hb;
+            pa.hbo2 = d_out->hbo2;
+            pa.thb = d_out->thb;
+            pa.so2 = d_out->so2;
+        }
+        if (launch_posterior(pa, p->use_mfma, s) != hipSuccess) return HB_ERR_DEVICE;
+    }
+    if (mark(2) != hipSuccess) return HB_ERR_DEVICE;
+    RecomposeArgs ra{};
+    ra.d = p->dims;
+    ra.lowpass = p->desc.lowpass;
+    ra.split = p->split;
+    ra.part = cb.part;
+    ra.z = cb.z;
+    ra.M = p->d_mf;
+    ra.det = cb.det;
+    ra.est = cb.est;
+    ra.thb_eps = (float)p->desc.thb_eps;
+    ra.hb = d_out->hb;
+    ra.hbo2 = d_out->hbo2;
+    ra.thb = d_out->thb;
+    ra.so2 = d_out->so2;
+    if (!fused && launch_recompose(n_frames, ra, s) != hipSuccess) return HB_ERR_DEVICE;
+    if (mark(3) != hipSuccess) return HB_ERR_DEVICE;
+    // Completion marker for hb_destroy (not recorded into a graph under capture).
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return HB_ERR_DEVICE;
+    if (cap == hipStreamCaptureStatusNone && hipEventRecord(p->done, s) != hipSuccess) return HB_ERR_DEVICE;
+    p->last_frames = n_frames;
+    return HB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -419,6 +566,7 @@ const char *hb_status_string(hb_status_t s) {
         case HB_ERR_DEVICE: return "HIP device error";
         case HB_ERR_ILL_POSED: return "Tikhonov system is singular";
         case HB_ERR_BATCH: return "n_frames exceeds the plan's max_batch";
+        case HB_ERR_SCRATCH: return "the call's buffers exceed the static scratch of hb_estimate_frames_noalloc";
     }
     return "unknown status";
 }
@@ -471,6 +619,13 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     if (st != HB_OK) {
         free_plan(p);
         return st;
+    }
+    // Device address of the static scratch, looked up here with the plan's
+    // device current so that hb_estimate_frames_noalloc never has to.  A
+    // failed lookup only disables that call (it then returns HB_ERR_DEVICE).
+    if (static_scratch(device, &p->scratch) != hipSuccess) {
+        (void)hipGetLastError();
+        p->scratch = nullptr;
     }
     p->info.grid_split = p->split;
     p->info.n_tiles = p->n_tiles;
@@ -604,112 +759,20 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
 
 hb_status_t hb_estimate_frames(hb_plan_t p, const void *d_frames, int32_t n_frames, const hb_maps_t *d_out,
                                void *stream) {
-    if (!p || !d_out) return HB_ERR_INVALID_ARG;
-    if (n_frames < 0) return HB_ERR_INVALID_ARG;
-    if (n_frames > p->desc.max_batch) return HB_ERR_BATCH;
-    if (!p->has_model) return HB_ERR_NO_FORWARD_MODEL;
-    if (n_frames == 0) return HB_OK;
-    if (!d_frames) return HB_ERR_INVALID_ARG;
-    if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
-    hipStream_t s = (hipStream_t)stream;
+    const hb_status_t st = check_call(p, d_frames, n_frames, d_out);
+    if (st != HB_OK || n_frames == 0) return st;
+    const CallBuffers cb{p->d_z, p->d_det, p->d_part, p->d_gref, p->d_est};
+    return estimate(p, d_frames, n_frames, d_out, (hipStream_t)stream, cb, true);
+}
 
-    hipEvent_t *ev = nullptr;
-    if (p->timing && p->timed_calls < kMaxTimedCalls) {
-        const size_t need = 4 * (size_t)(p->timed_calls + 1);
-        while (p->events.size() < need) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return HB_ERR_DEVICE;
-            p->events.push_back(e);
-        }
-        ev = &p->events[4 * (size_t)p->timed_calls];
-        p->timed_calls++;
-    }
-    auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
-
-    HaarArgs ha{};
-    ha.d = p->dims;
-    ha.dtype = p->desc.frame_dtype;
-    ha.floor = (float)p->desc.intensity_floor;
-    for (int k = 0; k < 3; ++k) ha.iref[k] = p->iref[k];
-    ha.M = p->d_mf;
-    ha.z = p->d_z;
-    ha.det = p->d_det;
-    ha.project = p->desc.illumination && p->desc.lowpass == HB_LOWPASS_BAYES;
-
-    if (mark(0) != hipSuccess) return HB_ERR_DEVICE;
-    if (launch_log_haar(d_frames, n_frames, ha, s) != hipSuccess) return HB_ERR_DEVICE;
-    if (mark(1) != hipSuccess) return HB_ERR_DEVICE;
-    bool fused = false;
-    if (p->desc.lowpass == HB_LOWPASS_BAYES) {
-        PosteriorArgs pa{};
-        pa.LL = p->dims.LL;
-        pa.hl = p->dims.hl;
-        pa.wl = p->dims.wl;
-        pa.n_frames = n_frames;
-        pa.z = p->d_z;
-        pa.supers = p->d_tiles;
-        pa.split_ops = p->d_split;
-        pa.n_supers = p->n_tiles;
-        pa.super_stride = super_floats(p->side);
-        pa.chunks_per_super = (p->side / 4) * (p->side / 4);
-        pa.split = p->split;
-        pa.scale = p->scale;
-        pa.skip_log2 = p->skip_log2;
-        pa.part = p->d_part;
-        pa.work = ev ? p->d_work : nullptr;
-        if (ev) p->full_pairs += (long long)n_frames * p->dims.LL * p->n_nodes;
-        if (p->d_gref) {
-            pa.gref = p->d_gref;
-            if (launch_reference(pa, s) != hipSuccess) return HB_ERR_DEVICE;
-        }
-        // One split, MFMA kernel, n <= 2: the posterior writes the maps.
-        fused = p->use_mfma && p->split == 1 && p->dims.levels <= 2;
-        if (fused) {
-            const int B = 1 << p->dims.levels;
-            auto fits = [&](int v) {
-                if (B % v) return false;
-                for (const float *m : {d_out->hb, d_out->hbo2, d_out->thb, d_out->so2})
-                    if (m && ((uintptr_t)m % (sizeof(float) * v)) != 0) return false;
-                return true;
-            };
-            pa.fuse = 1;
-            pa.vec = fits(4) ? 4 : (fits(2) ? 2 : 1);
-            pa.levels = p->dims.levels;
-            pa.H = p->dims.H;
-            pa.W = p->dims.W;
-            pa.det = p->d_det;
-            pa.est = p->d_est;
-            pa.thb_eps = (float)p->desc.thb_eps;
-            pa.hb = d_out->hb;
-            pa.hbo2 = d_out->hbo2;
-            pa.thb = d_out->thb;
-            pa.so2 = d_out->so2;
-        }
-        if (launch_posterior(pa, p->use_mfma, s) != hipSuccess) return HB_ERR_DEVICE;
-    }
-    if (mark(2) != hipSuccess) return HB_ERR_DEVICE;
-    RecomposeArgs ra{};
-    ra.d = p->dims;
-    ra.lowpass = p->desc.lowpass;
-    ra.split = p->split;
-    ra.part = p->d_part;
-    ra.z = p->d_z;
-    ra.M = p->d_mf;
-    ra.det = p->d_det;
-    ra.est = p->d_est;
-    ra.thb_eps = (float)p->desc.thb_eps;
-    ra.hb = d_out->hb;
-    ra.hbo2 = d_out->hbo2;
-    ra.thb = d_out->thb;
-    ra.so2 = d_out->so2;
-    if (!fused && launch_recompose(n_frames, ra, s) != hipSuccess) return HB_ERR_DEVICE;
-    if (mark(3) != hipSuccess) return HB_ERR_DEVICE;
-    // Completion marker for hb_destroy (not recorded into a graph under capture).
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return HB_ERR_DEVICE;
-    if (cap == hipStreamCaptureStatusNone && hipEventRecord(p->done, s) != hipSuccess) return HB_ERR_DEVICE;
-    p->last_frames = n_frames;
-    return HB_OK;
+hb_status_t hb_estimate_frames_noalloc(hb_plan_t p, const void *d_frames, int32_t n_frames,
+                                       const hb_maps_t *d_out, void *stream) {
+    const hb_status_t st = check_call(p, d_frames, n_frames, d_out);
+    if (st != HB_OK || n_frames == 0) return st;
+    if (!p->scratch) return HB_ERR_DEVICE;
+    CallBuffers cb{};
+    if (!carve_scratch(p, n_frames, (unsigned char *)p->scratch, cb)) return HB_ERR_SCRATCH;
+    return estimate(p, d_frames, n_frames, d_out, (hipStream_t)stream, cb, false);
 }
 
 hb_status_t hb_destroy(hb_plan_t p) {

@@ -34,6 +34,8 @@ HB_ERR_OUT_OF_MEMORY = -4
 HB_ERR_DEVICE = -5
 HB_ERR_ILL_POSED = -6
 HB_ERR_BATCH = -7
+HB_ERR_SCRATCH = -8
+HB_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 HB_F32, HB_F16, HB_BF16 = 0, 1, 2
 HB_LOWPASS_BAYES, HB_LOWPASS_TIKHONOV = 0, 1
@@ -86,6 +88,8 @@ _lib.hb_plan_create.argtypes = [ctypes.POINTER(hb_plan_desc_t), ctypes.c_int, ct
 _lib.hb_set_forward_model.argtypes = [_P, ctypes.POINTER(hb_forward_model_t)]
 _lib.hb_estimate_frames.argtypes = [_P, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(hb_maps_t),
                                     ctypes.c_void_p]
+_lib.hb_estimate_frames_noalloc.argtypes = [_P, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(hb_maps_t),
+                                            ctypes.c_void_p]
 _lib.hb_destroy.argtypes = [_P]
 _lib.hb_status_string.argtypes = [ctypes.c_int]
 _lib.hb_status_string.restype = ctypes.c_char_p
@@ -97,12 +101,12 @@ _lib.hb_plan_get_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.
 _lib.hb_debug_copy.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]
 _lib.hb_plan_get_work.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
 for _f in ("hb_plan_desc_default", "hb_plan_create", "hb_set_forward_model", "hb_estimate_frames",
-           "hb_destroy", "hb_plan_get_info", "hb_plan_set_timing", "hb_plan_get_timing", "hb_debug_copy",
+           "hb_estimate_frames_noalloc", "hb_destroy", "hb_plan_get_info", "hb_plan_set_timing", "hb_plan_get_timing", "hb_debug_copy",
            "hb_plan_get_work"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("hb_plan_desc_default", "hb_plan_create", "hb_set_forward_model", "hb_estimate_frames",
-            "hb_destroy", "hb_status_string", "hb_plan_device_bytes", "hb_plan_get_info",
+            "hb_estimate_frames_noalloc", "hb_destroy", "hb_status_string", "hb_plan_device_bytes", "hb_plan_get_info",
             "hb_plan_set_timing", "hb_plan_get_timing", "hb_debug_copy", "hb_plan_get_work")
 
 
@@ -154,6 +158,13 @@ def hb_estimate_frames(plan: int, d_frames: int, n_frames: int, maps: Sequence[i
     m = hb_maps_t(*[int(x) if x else None for x in maps])
     _check(_lib.hb_estimate_frames(_P(plan), ctypes.c_void_p(d_frames), n_frames, ctypes.byref(m),
                                    ctypes.c_void_p(stream)), "hb_estimate_frames")
+
+
+def hb_estimate_frames_noalloc(plan: int, d_frames: int, n_frames: int, maps: Sequence[int],
+                               stream: int = 0) -> None:
+    m = hb_maps_t(*[int(x) if x else None for x in maps])
+    _check(_lib.hb_estimate_frames_noalloc(_P(plan), ctypes.c_void_p(d_frames), n_frames, ctypes.byref(m),
+                                           ctypes.c_void_p(stream)), "hb_estimate_frames_noalloc")
 
 
 def hb_destroy(plan: int) -> None:
@@ -234,11 +245,13 @@ class Plan:
                              spectra.path_length_cm, getattr(spectra, "wavelength_nm", None))
         return self
 
-    def estimate(self, frames, maps: Sequence, stream=None) -> None:
+    def estimate(self, frames, maps: Sequence, stream=None, noalloc: bool = False) -> None:
         """frames: device tensor [n][H][W][3] (float32/float16, or int16/uint16
         bit patterns for bfloat16); maps: four device float32 tensors
         [n][H][W] or None.  Shapes, dtypes, devices and contiguity are checked
-        here, since the library receives bare pointers."""
+        here, since the library receives bare pointers.  noalloc: call
+        hb_estimate_frames_noalloc (intermediate buffers in the library's
+        static scratch) instead of hb_estimate_frames."""
         import torch
         d = self.desc
         want = {HB_F32: (torch.float32,), HB_F16: (torch.float16,),
@@ -264,7 +277,8 @@ class Plan:
         if stream is None:
             stream = torch.cuda.current_stream(frames.device)
         sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
-        hb_estimate_frames(self.handle, frames.data_ptr(), n, ptrs, sp)
+        call = hb_estimate_frames_noalloc if noalloc else hb_estimate_frames
+        call(self.handle, frames.data_ptr(), n, ptrs, sp)
 
     def info(self) -> Dict[str, object]:
         return hb_plan_get_info(self.handle)

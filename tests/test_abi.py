@@ -73,7 +73,7 @@ int main(void) {
 
 
 def test_status_strings(hb):
-    for s in range(0, -8, -1):
+    for s in range(0, -9, -1):
         assert hb.hb_status_string(s) and hb.hb_status_string(s) != "unknown status"
     assert hb.hb_status_string(-99) == "unknown status"
 
@@ -142,3 +142,15 @@ def test_library_has_no_cpu_fallback_symbols(hb):
     """The product path is the HIP library; nothing in it links the oracle."""
     out = subprocess.run(["nm", "-D", "--defined-only", hb.LIB_PATH], capture_output=True, text=True).stdout
     assert "orc_" not in out
+
+
+def test_noalloc_scratch_size_matches_header(hb):
+    m = re.search(r"#define HB_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == hb.HB_NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_rejects_null_plan_on_the_host(hb):
+    maps = hb.hb_maps_t()
+    for fn in (hb._lib.hb_estimate_frames, hb._lib.hb_estimate_frames_noalloc):
+        assert fn(None, None, 1, ctypes.byref(maps), None) == hb.HB_ERR_INVALID_ARG
+        assert fn(None, None, 1, None, None) == hb.HB_ERR_INVALID_ARG
