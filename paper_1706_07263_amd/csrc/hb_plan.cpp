@@ -557,7 +557,11 @@ hb_status_t hb_plan_desc_default(hb_plan_desc_t *d) {
 }
 
 const char *hb_status_string(hb_status_t s) {
-    switch (s) {
+    // C callers may pass any int; read it as one (an out-of-range value of the
+    // enum type is not a valid C++ value).
+    int v;
+    std::memcpy(&v, &s, sizeof(v));
+    switch (v) {
         case HB_OK: return "ok";
         case HB_ERR_INVALID_ARG: return "invalid argument";
         case HB_ERR_SHAPE: return "invalid frame shape (width and height must be positive multiples of 2^levels)";
