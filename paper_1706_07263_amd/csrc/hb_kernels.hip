@@ -1044,10 +1044,10 @@ __device__ __forceinline__ void fused_maps(const PosteriorArgs &a, const WaveWor
 // (nodes as rows, pixels as columns) from exact three-part bf16 splits of the
 // FP32 operands: every product except the smallest (u3 v3), in half the
 // cycles of the FP32 16x16x4 MFMA.  The node operand (1 KB per chunk) is
-// loaded once for all PB blocks.  Each lane then holds 1 pixel x the 4 nodes
-// of one chunk row (lane l: pixel l % 16, THb row l / 16, SO2 offsets 0..3)
-// and runs the exponentials and the moments on the VALU.
-// Two pixel blocks per wave (an 8 x 4 tile) at six waves per SIMD (78 VGPRs,
+// loaded once for all PB blocks.  Each lane then holds 1 pixel x the 4
+// nodes of one chunk row (lane l: pixel l % 16, THb row l / 16, SO2 offsets
+// 0..3) and runs the exponentials and the moments on the VALU.
+// Two pixel blocks per wave (an 8 x 4 tile) at six waves per SIMD (80 VGPRs,
 // no spills) measured fastest on the 1080p workload.
 template <int PB>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_posterior(PosteriorArgs a) {
@@ -1056,6 +1056,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
     const int lane = threadIdx.x & 63;
     const int lp = lane & 15, lk = lane >> 4;
     const WaveWork w = wave_work<PW>(a);
+    // Tiles below the last row of the frame (the workgroup grid rounds the
+    // rows up) hold no pixel: nothing to do.
+    if (w.r0 >= a.hl) return;
     const float *zf = a.z + (size_t)w.f * 6 * a.LL;
     const float sc = a.scale;
 
@@ -1127,6 +1130,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
         const_cast<void *>(a.split_ops), (short)0, a.n_supers * a.chunks_per_super * kSplitChunkBytes, kBufferWord3);
     const __amdgpu_buffer_rsrc_t super_rsrc = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float *>(a.supers), (short)0, a.n_supers * a.super_stride * 4, kBufferWord3);
+    // A super-tile holds at most 64 chunks (side <= 32): one chunk per lane.
+    const int ct = min(lane, a.chunks_per_super - 1);
+    const bool chunk_lane = lane < a.chunks_per_super;
     // Super-tiles are tested one per lane; the kept ones are walked in order.
     for (int g = w.s0; g < w.s1; g += 64) {
       float rbox[6];
@@ -1136,7 +1142,12 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
         const int si = g + __builtin_ctzll(smask);
         smask &= smask - 1;
         const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+        const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
+        // chunk tests, one chunk per lane
         wave_super_bound(a, si, zlo, zhi, rbox);
+        const unsigned long long mask =
+            __ballot(chunk_lane && box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > nskip);
+        if (mask == 0) continue;
         const int kk = lk < 3 ? lk : 0;
         const float ch = T[kk], cl = T[3 + kk];
         bf16x8 av[PB];
@@ -1152,64 +1163,57 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
         float L0[PB], L1[PB], L2[PB];
 #pragma unroll
         for (int b = 0; b < PB; ++b) L0[b] = L1[b] = L2[b] = 0.0f;
-        const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
         const int s_first = si * a.chunks_per_super;   // first chunk of the super-tile in the split table
         // byte offset of the first chunk's row coefficients in the super-tile table
         const int c_first = (si * a.super_stride + kSupHdr + kMaxProbes * kProbeFloats + 104) * 4;
-        for (int cg = 0; cg < a.chunks_per_super; cg += 64) {
-            const int ct = min(cg + lane, a.chunks_per_super - 1);
-            const bool keep = cg + lane < a.chunks_per_super &&
-                              box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > nskip;
-            unsigned long long mask = __ballot(keep);
-            if (mask == 0) continue;
-            // Walk the kept chunks with two operand buffers: the next chunk's
-            // operands are in flight while the current one is evaluated.
-            // The loads are issued unconditionally (the last chunk is simply
-            // loaded again), so the wait counts match on every path and a
-            // wait for the current chunk never waits for the next one.
-            int last = cg;
-            auto take = [&](bf16x8 &bv, f32x3 &qm) -> bool {
-                const bool got = mask != 0;
-                last = got ? cg + __builtin_ctzll(mask | (1ull << 63)) : last;
-                mask &= mask - 1;
-                bv = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
-                                                    split_rsrc, lane * kSplitLaneBytes,
-                                                    (s_first + last) * kSplitChunkBytes, 0));
-                qm = __builtin_bit_cast(f32x3, __builtin_amdgcn_raw_buffer_load_b96(
-                                                   super_rsrc, lk * 16, c_first + last * (kChunkFloats * 4), 0));
-                // keep these loads ahead of the evaluation that follows
-                __builtin_amdgcn_sched_barrier(0);
-                return got;
-            };
-            // Weights of the row's four nodes (SO2 offsets s = 0..3): their sum
-            // W0 and first moment W1 = sum s w_s give the row's Hb moment
-            // through the affine row coefficients, and W0 its THb moment (THb
-            // is constant along the row); HbO2 = THb - Hb after the super-tile.
-            auto eval = [&](const bf16x8 &bv, const f32x3 &qm) {
-                ++executed;
+        // Walk the kept chunks with two operand buffers: the next chunk's
+        // operands are in flight while the current one is evaluated.  The
+        // loads are issued unconditionally (the last chunk is simply loaded
+        // again), so the wait counts match on every path and a wait for the
+        // current chunk never waits for the next one.
+        unsigned long long walk = mask;
+        int last = 0;
+        auto take = [&](bf16x8 &bv, f32x3 &qm) -> bool {
+            const bool got = walk != 0;
+            last = got ? __builtin_ctzll(walk | (1ull << 63)) : last;
+            walk &= walk - 1;
+            bv = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
+                                                split_rsrc, lane * kSplitLaneBytes,
+                                                (s_first + last) * kSplitChunkBytes, 0));
+            qm = __builtin_bit_cast(f32x3, __builtin_amdgcn_raw_buffer_load_b96(
+                                               super_rsrc, lk * 16, c_first + last * (kChunkFloats * 4), 0));
+            // keep these loads ahead of the evaluation that follows
+            __builtin_amdgcn_sched_barrier(0);
+            return got;
+        };
+        // Weights of the row's four nodes (SO2 offsets s = 0..3): their sum
+        // W0 and first moment W1 = sum s w_s give the row's Hb moment
+        // through the affine row coefficients, and W0 its THb moment (THb
+        // is constant along the row); HbO2 = THb - Hb after the super-tile.
+        auto eval = [&](const bf16x8 &bv, const f32x3 &qm) {
+            ++executed;
 #pragma unroll
-                for (int b = 0; b < PB; ++b) {
-                    const f32x4 d = mfma_16x16x32_bf16(bv, av[b], zero4);
-                    const float w0 = __builtin_amdgcn_exp2f(d[0]), w1 = __builtin_amdgcn_exp2f(d[1]);
-                    const float w2 = __builtin_amdgcn_exp2f(d[2]), w3 = __builtin_amdgcn_exp2f(d[3]);
-                    const float W0 = (w0 + w1) + (w2 + w3);
-                    const float W1 = fmaf(3.0f, w3, fmaf(2.0f, w2, w1));
-                    L0[b] += W0;
-                    L1[b] = fmaf(qm.x, W0, fmaf(qm.y, W1, L1[b]));
-                    L2[b] = fmaf(qm.z, W0, L2[b]);
-                }
-            };
-            bf16x8 bA, bB;
-            f32x3 qA, qB;
-            take(bA, qA);
-            while (true) {
-                const bool gotB = take(bB, qB);
-                eval(bA, qA);
-                if (!gotB) break;
-                const bool gotA = take(bA, qA);
-                eval(bB, qB);
-                if (!gotA) break;
+            for (int b = 0; b < PB; ++b) {
+                const f32x4 d = mfma_16x16x32_bf16(bv, av[b], zero4);
+                const float w0 = __builtin_amdgcn_exp2f(d[0]), w1 = __builtin_amdgcn_exp2f(d[1]);
+                const float w2 = __builtin_amdgcn_exp2f(d[2]), w3 = __builtin_amdgcn_exp2f(d[3]);
+                const float W0 = (w0 + w1) + (w2 + w3);
+                const float W1 = fmaf(3.0f, w3, fmaf(2.0f, w2, w1));
+                L0[b] += W0;
+                L1[b] = fmaf(qm.x, W0, fmaf(qm.y, W1, L1[b]));
+                L2[b] = fmaf(qm.z, W0, L2[b]);
             }
+        };
+        bf16x8 bA, bB;
+        f32x3 qA, qB;
+        take(bA, qA);
+        while (true) {
+            const bool gotB = take(bB, qB);
+            eval(bA, qA);
+            if (!gotB) break;
+            const bool gotA = take(bA, qA);
+            eval(bB, qB);
+            if (!gotA) break;
         }
         const float chb = T[6], cox = T[7];
 #pragma unroll
@@ -1265,6 +1269,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
     constexpr int PW = 64;
     const int lane = threadIdx.x & 63;
     const WaveWork w = wave_work<PW>(a);
+    if (w.r0 >= a.hl) return;   // a tile below the frame's last row holds no pixel
     const float *zf = a.z + (size_t)w.f * 6 * a.LL;
     long long p;
     const bool valid = wave_pixel(a, w, lane, p);
