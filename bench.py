@@ -77,7 +77,7 @@ def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--levels", type=int, default=2)
@@ -206,12 +206,17 @@ def cpu_baseline(target_s: float, levels: int, grid: int, quiet: bool):
     dt = timed(rows, fr)
     lp = (rows // b) * (1920 // b)
     if rows == 1080 and dt < 0.5 * target_s:
-        n = int(min(8, max(2, round(target_s / dt))))
-        frs = render_video(list(range(n)), "f32").astype(np.float64)
-        dt = timed(1080, frs)
-        out = {"value": n / dt, "unit": "frames/s", "cores": orc.threads(), "kind": "oracle",
-               "sample": f"frames 0..{n - 1} (1920x1080, {(1080 // b) * (1920 // b)} low-pass pixels x "
-                         f"{grid * grid} nodes each), {dt:.2f} s"}
+        # whole video frames 0, 150, 299 (more, spread over the sequence, if
+        # they take less than the target), each timed alone; the median
+        idx = [0, 150, 299] if dt * 3 >= 0.5 * target_s else \
+            [int(i * 299 / (n - 1)) for n in [int(min(9, round(target_s / dt)))] for i in range(n)]
+        frs = render_video(idx, "f32").astype(np.float64)
+        times = [timed(1080, frs[i:i + 1]) for i in range(len(idx))]
+        dt = float(np.median(times))
+        out = {"value": 1.0 / dt, "unit": "frames/s", "cores": orc.threads(), "kind": "oracle",
+               "sample": f"video frames {', '.join(map(str, idx))} (1920x1080, {(1080 // b) * (1920 // b)} "
+                         f"low-pass pixels x {grid * grid} nodes each), each timed alone: median {dt:.2f} s "
+                         f"of {', '.join(f'{t:.2f}' for t in times)} s"}
     else:
         out = {"value": (rows / 1080.0) / dt, "unit": "frames/s", "cores": orc.threads(), "kind": "oracle",
                "sample": f"rows 0..{rows - 1} of frame 0 (1920x{rows} px, {lp} low-pass pixels x "
@@ -251,22 +256,32 @@ def make_desc(hb, a, W, H, B, dtype=None, **kw):
                         grid_split=kw.pop("grid_split", a.split), **kw)
 
 
-def run_timed(hb, torch, plan, frames, maps, stream, steps, warmup):
+def run_timed(hb, torch, plan, frames, maps, stream, steps, warmup, call_ms=None):
     """Warm-up calls, then `steps` calls timed on the host clock between device
     synchronisations, with the plan's per-kernel HIP events and pair counter.
-    Returns (seconds, stage ms per call, evaluated pairs per posterior launch)."""
+    Returns (seconds, stage ms per call, evaluated pairs per posterior launch,
+    full-grid pairs per launch).  With a list `call_ms`, HIP events on the
+    launch stream around every timed call append each call's milliseconds."""
     with torch.cuda.stream(stream):
         for _ in range(warmup):
             plan.estimate(frames, maps, stream)
     torch.cuda.synchronize()
     hb.hb_plan_set_timing(plan.handle, True)
     torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)] if call_ms is not None else None
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        for _ in range(steps):
+        for i in range(steps):
+            if ev:
+                ev[i][0].record(stream)
             plan.estimate(frames, maps, stream)
+            if ev:
+                ev[i][1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if ev:
+        call_ms.extend(e0.elapsed_time(e1) for e0, e1 in ev)
     ms, launches = hb.hb_plan_get_timing(plan.handle)
     evaluated, full = hb.hb_plan_get_work(plan.handle)
     hb.hb_plan_set_timing(plan.handle, False)
@@ -400,29 +415,32 @@ SERVE_MAX_BATCH = {(480, 640): 8, (1024, 1280): 6, (1080, 1920): 4, (2160, 3840)
 
 
 def serving(a):
-    """16 Poisson camera streams of mixed resolution, FP16 frames, with
-    a.serve_sources distinct frames per class: at 30 frames/s per stream;
-    then the same mix offered far above capacity for a short run, whose
-    served rate is the saturated throughput (every lane busy, full batches);
-    then a run offered a.serve_load of that throughput (rho), stepped down to
-    0.5 if the queues do not keep up."""
+    """16 Poisson camera streams of mixed resolution, with a.serve_sources
+    distinct frames per class: FP16 frames at 30 frames/s per stream; the
+    plain FP32 path on the same streams (FP32 frames, twice the bytes per
+    frame); then the FP16 mix offered far above capacity for a short run,
+    whose served rate is the saturated throughput (every lane busy, full
+    batches); then a run offered a.serve_load of that throughput (rho),
+    stepped down to 0.5 if the queues do not keep up."""
     import torch
     from paper_1706_07263_amd import synth
     from paper_1706_07263_amd.serve import GpuExecutor, Server, render_sources, workload_requests
     dur = a.serve_warmup + a.serve_seconds
-    _, offered = workload_requests(dur, n_sources=a.serve_sources)
-    classes = sorted(offered, key=lambda c: c.pixels)
     n_streams = sum(cnt for cnt, *_ in synth.SERVE_CLASSES)
-    log(f"serving: rendering {len(classes)} x {a.serve_sources} source frames", a.quiet)
-    raw = render_sources(classes, n_sources=a.serve_sources, workers=8)
-    sources = {c: torch.from_numpy(v).pin_memory() for c, v in raw.items()}
-    ex = GpuExecutor(synth.spectra(), sources)
-    srv = Server(ex, {c: SERVE_MAX_BATCH[(c.height, c.width)] for c in classes},
-                 hbm_budget=int(a.serve_budget_gib * (1 << 30)), offered=offered, max_lanes=2)
-    log(f"serving: {len(srv.lanes)} lanes, {srv.used / 2**30:.2f} GiB", a.quiet)
 
-    def point(fps, duration, warmup):
-        reqs, off = workload_requests(duration, fps=fps, n_sources=a.serve_sources)
+    def server(dtype):
+        _, offered = workload_requests(dur, n_sources=a.serve_sources, dtype=dtype)
+        classes = sorted(offered, key=lambda c: c.pixels)
+        log(f"serving: rendering {len(classes)} x {a.serve_sources} {dtype} source frames", a.quiet)
+        raw = render_sources(classes, n_sources=a.serve_sources, workers=8)
+        sources = {c: torch.from_numpy(v).pin_memory() for c, v in raw.items()}
+        srv = Server(GpuExecutor(synth.spectra(), sources), {c: SERVE_MAX_BATCH[(c.height, c.width)] for c in classes},
+                     hbm_budget=int(a.serve_budget_gib * (1 << 30)), offered=offered, max_lanes=2)
+        log(f"serving {dtype}: {len(srv.lanes)} lanes, {srv.used / 2**30:.2f} GiB", a.quiet)
+        return srv
+
+    def point(srv, fps, duration, warmup, dtype="f16"):
+        reqs, off = workload_requests(duration, fps=fps, n_sources=a.serve_sources, dtype=dtype)
         rep = srv.run(reqs, warmup_s=warmup)
         out = rep.summary()
         out["fps_per_stream"] = round(fps, 2)
@@ -431,24 +449,33 @@ def serving(a):
         out["offered_mpixel_per_s"] = round(sum(r.cls.pixels for r in reqs) / duration / 1e6, 1)
         out["window_s"] = round(duration - warmup, 3)
         out["sources_per_class"] = a.serve_sources
-        log(f"serving at {fps:.1f} frames/s per stream: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, "
+        out["frame_dtype"] = dtype
+        log(f"serving {dtype} at {fps:.1f} frames/s per stream: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, "
             f"{out['frames_per_s']} frames/s served, {out['mpixel_per_s']} Mpixel/s, "
             f"mean batch {out['mean_batch']}, max queue {out['max_queue']}", a.quiet)
         return out
 
-    base = point(30.0, dur, a.serve_warmup)
+    srv32 = server("f32")
+    plain = point(srv32, 30.0, dur, a.serve_warmup, "f32")
+    srv32.close()
+    del srv32
+    torch.cuda.empty_cache()
+    srv = server("f16")
+    base = point(srv, 30.0, dur, a.serve_warmup)
     base["streams"] = n_streams
+    base["fp32_path"] = {k: plain[k] for k in ("frames", "p50_ms", "p99_ms", "max_ms", "frames_per_s",
+                                               "mpixel_per_s", "hbm_bytes", "mean_batch", "per_class")}
     # Saturated throughput: the mix offered far above what the lanes can
     # serve (1000 frames/s per stream, several times the capacity) for one
     # second; every frame served over the whole run (arrivals end long before
     # the queues drain, so every lane stays busy) over the run's length is
     # the capacity.
     hi = 1000.0
-    sat = point(hi, 1.0, 0.0)
+    sat = point(srv, hi, 1.0, 0.0)
     cap = sat["frames_per_s"] / n_streams          # frames/s per stream at saturation
     loaded = None
     for rho in (a.serve_load, 0.5):
-        loaded = point(rho * cap, dur, a.serve_warmup)
+        loaded = point(srv, rho * cap, dur, a.serve_warmup)
         loaded["rho"] = rho
         # kept up: served what was offered, and no queue beyond a few batches
         if loaded["frames_per_s"] >= 0.95 * loaded["offered_frames_per_s"] and loaded["p99_ms"] < 100.0:
@@ -539,8 +566,9 @@ def main():
     stream = torch.cuda.Stream(dev)
 
     log(f"warmup {a.warmup}, timed {a.steps}", a.quiet)
+    call_ms = []
     elapsed, per, eval_per_launch, full_per_launch = run_timed(hb, torch, plan, frames, maps, stream,
-                                                               a.steps, a.warmup)
+                                                               a.steps, a.warmup, call_ms)
     plan.close()
     log(f"timed {a.steps} steps in {elapsed:.3f} s; stage ms {per}", a.quiet)
 
@@ -578,7 +606,9 @@ def main():
         "frac_of_fp32_vector_peak": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
         "frac_of_unpacked_fp32_peak": round(achieved / FP32_UNPACKED_PEAK_TFLOPS, 4),
     }
-    stage = {"log_haar_ms": per[0], "posterior_ms": per[1], "recompose_ms": per[2], "call_ms": per[3]}
+    stage = {"log_haar_ms": per[0], "posterior_ms": per[1], "recompose_ms": per[2], "call_ms": per[3],
+             "call_ms_median": float(np.median(call_ms)), "call_ms_min": float(np.min(call_ms)),
+             "call_ms_max": float(np.max(call_ms))}
     # K1 algorithmic bytes: frames read; detail part (8 B/px) and the
     # double-float low-pass observation (24 B per low-pass pixel) written.
     k1_bytes = B * H * W * ((12 if a.dtype == "f32" else 6) + 8) + B * LL * 24
@@ -668,6 +698,11 @@ def main():
         "mpixel_per_s": round(fps * H * W / 1e6, 2),
         "stages_ms_per_call": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stage.items()},
         "roofline": roofline,
+        "hbm_roofline": {"bound": "hbm", "kernel": "k_log_haar_reg", "achieved": round(stage["log_haar_GBps"], 1),
+                         "peak": 8000.0, "unit": "GB/s", "frac": round(stage["log_haar_GBps"] / 8000.0, 4),
+                         "algorithmic_bytes_per_launch": int(k1_bytes),
+                         "note": "log-attenuation, Haar, Tikhonov and the detail part: frames read, detail part "
+                                 "and double-float observation written"},
         "posterior_modes": modes,
         "ceiling": ceil,
         "batch_sweep_frames_per_s": sweep,
