@@ -39,8 +39,7 @@ FLOPS_PER_PAIR = 15
 FLOPS_PER_PAIR_MFMA = 10
 FLOPS_PER_PAIR_VALU = 5
 EXPS_PER_PAIR = 1
-FP32_VECTOR_PEAK_TFLOPS = 157.3        # packed FP32 (not used by this build)
-FP32_UNPACKED_PEAK_TFLOPS = 78.65      # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 157.3        # MI355X FP32 vector peak (context; the measured mix ceiling is the peak)
 # Roofline of the posterior: its chunk evaluation (one 16-node chunk against
 # one 16-pixel block = 256 pairs: one bf16 16x16x32 MFMA, four v_exp_f32 and
 # nine FP32 VALU instructions) measured with no memory traffic by the `mix`
@@ -604,7 +603,6 @@ def main():
         "flops_per_pair": FLOPS_PER_PAIR, "flops_per_pair_on_mfma": FLOPS_PER_PAIR_MFMA,
         "flops_per_pair_on_valu": FLOPS_PER_PAIR_VALU, "exps_per_pair": EXPS_PER_PAIR,
         "frac_of_fp32_vector_peak": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-        "frac_of_unpacked_fp32_peak": round(achieved / FP32_UNPACKED_PEAK_TFLOPS, 4),
     }
     stage = {"log_haar_ms": per[0], "posterior_ms": per[1], "recompose_ms": per[2], "call_ms": per[3],
              "call_ms_median": float(np.median(call_ms)), "call_ms_min": float(np.min(call_ms)),
