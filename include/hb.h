@@ -125,13 +125,18 @@ typedef struct {
     double mu_ref[3];     /* centring offset: -ln of the float32 reference intensities                 */
     int32_t grid_split;   /* posterior grid split in use                                                */
     int32_t n_tiles;      /* grid super-tiles                                                           */
-    int32_t posterior_kernel; /* 0 = MFMA logits, 1 = direct VALU (grids too coarse for the former)     */
+    int32_t posterior_kernel; /* 0 = MFMA logits, 1 = direct VALU (grids too coarse for the former),
+                                 2 = direct VALU with double-float logits (grids whose neighbouring nodes
+                                 are too far apart for float32 logits: direct_index > 3800)             */
     int64_t n_nodes;
     double skip_log2;     /* T: chunks whose logit bound lies more than T below the reference are skipped
                              (+inf: nothing is skipped)                                                   */
     double skip_bound;    /* uM, the stated bound on the posterior-mean change from skipping (0: exact)  */
     double mfma_index;    /* R^2 h: squared super-tile radius (scaled log-attenuation units) times the
                              node spacing (uM).  The MFMA kernel runs when it is <= 700                   */
+    double direct_index;  /* max over neighbouring grid nodes of their squared scaled distance times their
+                             largest Hb/HbO2 difference (uM); float32 logits can move a posterior mean by
+                             about 8e-9 times this                                                        */
 } hb_plan_info_t;
 
 /* Fill `desc` with defaults: 64x64, 1 level, FP32, max_batch 1, grid 128x128

@@ -63,6 +63,17 @@ constexpr int kSplitChunkBytes = 64 * kSplitLaneBytes;
 // and 1000 it reached 8.0e-5 uM (sigma 0.004 on a 256 x 256 grid), too
 // close to the 1e-4 uM tolerance.
 constexpr double kMfmaPrecisionBudget = 700.0;
+// Precision rule for the direct kernel.  Its float32 difference-form logit
+// of a node at scaled distance d from the observation carries an absolute
+// error of a few d^2 u; for a pixel between two neighbouring nodes at scaled
+// distance D apart, whose Hb/HbO2 differ by dc uM, the posterior mean then
+// moves by up to about 8e-9 D^2 dc uM (measured 1.4e-4 uM on a grid with
+// four THb nodes 68 uM apart).  Plans whose direct index max(D^2 dc) exceeds
+// kDirectPrecisionBudget (8e-9 x 3800 = 3e-5 uM) form the logits from
+// double-float coordinate differences instead.
+constexpr double kDirectPrecisionBudget = 3800.0;
+// Low parts of a chunk's node coordinates (3 coordinates x 16 nodes).
+constexpr int kLoFloats = 48;
 
 // Posterior chunk skipping.  exp2 of anything below -kExactSkipLog2 is exactly
 // 0 in float32 (the smallest subnormal is 2^-149; the margin covers rounding
@@ -148,6 +159,8 @@ struct PosteriorArgs {
     float skip_log2;         // chunks bounded more than this below the reference are skipped
     float *gref;             // [n][LL] best probe logit over the whole grid, or null (one split)
     float *part;             // [n][split][kPartFields][LL]
+    const float *lo;         // direct kernel: [chunk][kLoFloats] coordinate low parts for
+                             // double-float logits, or null for float32 logits
     unsigned long long *work;  // optional: pairs evaluated (pixel x node), added per wave
     // Fused recomposition (one split, MFMA kernel, levels <= 2): the kernel
     // writes the low-pass estimate and the maps itself instead of partials.

@@ -9,7 +9,8 @@
 //   K2  k_posterior         posterior mean over the THb x SO2 grid on the
 //                           low-pass band (MFMA logits); with one split it
 //                           also writes the maps                   (Fig. 1)
-//       k_posterior_direct  the same with VALU logits (coarse grids, small sigma)
+//       k_posterior_direct  the same with VALU logits (coarse grids, small sigma;
+//                           double-float logits for the coarsest)
 //   K3  k_recompose         split merge plus detail part to the THb/SO2 maps
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -1261,10 +1262,36 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
     }
 }
 
+// Logit minus the reference, nm - |r - v_j|^2 (nm = -m), with r and node j's
+// coordinates v_j = C + LO held as double-floats: the differences, their
+// squares and the sum carry their rounding errors, so the result is exact to
+// a float32 rounding of itself (a float32 difference form rounds at the
+// scale of |r| and |v_j| instead, which coarse grids make large).
+__device__ __forceinline__ float df_logit(const float rh[3], const float rl[3], const float *__restrict__ C,
+                                          const float *__restrict__ LO, int j, float nm) {
+#pragma clang fp contract(off)
+    float sh = 0.0f, sl = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float dh, e;
+        two_sum(rh[k], -C[16 * k + j], dh, e);
+        const float dl = e + (rl[k] - LO[16 * k + j]);
+        const float q = dh * dh;
+        const float qe = fmaf(2.0f * dh, dl, fmaf(dh, dh, -q));
+        float s, es;
+        two_sum(sh, q, s, es);
+        sh = s;
+        sl += es + qe;
+    }
+    return (nm - sh) - sl;
+}
+
 // Direct kernel: one LL pixel per lane, logits in the difference form
-// t - m = -(r - v_g)^2 - m on the VALU with wave-uniform (scalar) node loads.
-// Skipping, the global reference and the exact maximum over kept chunks are
-// as in the MFMA kernel.
+// t - m = -(r - v_g)^2 - m on the VALU with wave-uniform (scalar) node loads;
+// PRECISE: from double-float differences (df_logit), for grids whose nodes
+// are too far apart for float32 logits.  Skipping, the global reference and
+// the exact maximum over kept chunks are as in the MFMA kernel.
+template <bool PRECISE>
 __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArgs a) {
     constexpr int PW = 64;
     const int lane = threadIdx.x & 63;
@@ -1298,8 +1325,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
             smask &= smask - 1;
             const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
             wave_super_bound(a, si, zlo, zhi, rbox);
-            float r[3];
-            recentre(T, ph, pl, r);
+            float r[3], rh[3], rl[3];
+            if (PRECISE) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    float sk, e;
+                    two_sum(ph[k], -T[k], sk, e);
+                    fast_two_sum(sk, e + (pl[k] - T[3 + k]), rh[k], rl[k]);
+                }
+            } else {
+                recentre(T, ph, pl, r);
+            }
             float L0 = 0.f, L1 = 0.f, L2 = 0.f;
             const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
             for (int cg = 0; cg < a.chunks_per_super; cg += 64) {
@@ -1307,15 +1343,23 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
                 unsigned long long mask = __ballot(cg + lane < a.chunks_per_super &&
                                                    box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > nskip);
                 while (mask) {
-                    const float *__restrict__ C = C0 + (size_t)(cg + __builtin_ctzll(mask)) * kChunkFloats;
+                    const int ci = cg + __builtin_ctzll(mask);
+                    const float *__restrict__ C = C0 + (size_t)ci * kChunkFloats;
+                    const float *__restrict__ LO = PRECISE ? a.lo + ((size_t)si * a.chunks_per_super + ci) * kLoFloats
+                                                           : nullptr;
                     mask &= mask - 1;
                     ++executed;
 #pragma unroll
                     for (int j = 0; j < kChunkNodes; ++j) {
-                        const float d0 = r[0] - C[j], d1 = r[1] - C[16 + j], d2 = r[2] - C[32 + j];
-                        float t = fmaf(-d0, d0, nm);
-                        t = fmaf(-d1, d1, t);
-                        t = fmaf(-d2, d2, t);
+                        float t;
+                        if (PRECISE) {
+                            t = df_logit(rh, rl, C, LO, j, nm);
+                        } else {
+                            const float d0 = r[0] - C[j], d1 = r[1] - C[16 + j], d2 = r[2] - C[32 + j];
+                            t = fmaf(-d0, d0, nm);
+                            t = fmaf(-d1, d1, t);
+                            t = fmaf(-d2, d2, t);
+                        }
                         const float wt = __builtin_amdgcn_exp2f(t);
                         L0 += wt;
                         L1 = fmaf(wt, C[64 + j], L1);
@@ -1457,8 +1501,10 @@ hipError_t launch_posterior(const PosteriorArgs &a, bool mfma, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     if (mfma)
         hipLaunchKernelGGL(k_posterior<kPixelBlocks>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
+    else if (a.lo)
+        hipLaunchKernelGGL(k_posterior_direct<true>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(k_posterior_direct, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
+        hipLaunchKernelGGL(k_posterior_direct<false>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ struct hb_plan_s {
     int side = 8;
     double radius = 0;        // largest super-tile radius, scaled units
     bool use_mfma = true;
+    bool precise = false;       // direct kernel with double-float logits
     int n_tiles = 0;      // super-tiles
     long long n_nodes = 0;
     bool has_model = false;
@@ -39,6 +40,7 @@ struct hb_plan_s {
     size_t k0_in = 0;         // doubles of K0 input
     float *d_mf = nullptr;    // FP32 M (6) + low-pass Tikhonov offset (2)
     float *d_tiles = nullptr;   // super-tile table
+    float *d_lo = nullptr;      // low parts of the node coordinates (double-float direct logits)
     void *d_split = nullptr;    // split bf16 A operands of the chunks
     float *d_z = nullptr;
     float2 *d_det = nullptr;
@@ -139,6 +141,7 @@ void free_plan(hb_plan_s *p) {
     (void)hipFree(p->d_k0);
     (void)hipFree(p->d_mf);
     (void)hipFree(p->d_tiles);
+    (void)hipFree(p->d_lo);
     (void)hipFree(p->d_split);
     (void)hipFree(p->d_z);
     (void)hipFree(p->d_det);
@@ -180,8 +183,16 @@ struct ForwardModel {
 // super-tile centre in the MFMA operand layout, plus moments, boxes and probes.
 // With the illumination term the node vectors are projected onto the plane
 // orthogonal to (1,1,1), as the observations are.
+//
+// `lo` receives, per chunk, the low parts of the stored node coordinates
+// ([chunk][coordinate k][node j], 48 floats: the FP64 relative coordinate
+// minus its float32 value), for the direct kernel's double-float logits.
+// `direct_index` receives max over neighbouring nodes of the squared scaled
+// distance between them times their largest Hb/HbO2 difference (uM): with
+// float32 logits the posterior mean of a pixel between two such nodes can
+// move by about 8e-9 times this.
 double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const double mu_ref[3], double scale,
-                    int side, std::vector<float> &table) {
+                    int side, std::vector<float> &table, std::vector<float> &lo, double &direct_index) {
     const bool project = d.illumination && d.lowpass == HB_LOWPASS_BAYES;
     const int GT = d.grid_thb, GS = d.grid_so2;
     const int nsa = (GT + side - 1) / side, nss = (GS + side - 1) / side;
@@ -189,7 +200,8 @@ double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const doubl
     const int stride = super_floats(side);
     const int cps = side / 4;  // chunks per super-tile side
     table.assign((size_t)n_sup * stride, 0.0f);
-    std::vector<double> radius(n_sup, 0.0);
+    lo.assign((size_t)n_sup * cps * cps * kLoFloats, 0.0f);
+    std::vector<double> radius(n_sup, 0.0), index(n_sup, 0.0);
     auto work = [&](int s_begin, int s_end) {
         std::vector<double> mu((size_t)side * side * 3), chb((size_t)side * side), cox((size_t)side * side);
         std::vector<char> real((size_t)side * side);
@@ -235,11 +247,27 @@ double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const doubl
             }
             const float chb_c = (float)(mhb / nreal), cox_c = (float)(mox / nreal);
             auto rel = [&](int n, int k) { return mu[3 * n + k] - cen_d[k]; };
+            // neighbouring nodes inside the super-tile (both grid directions)
+            for (int i = 0; i < side; ++i)
+                for (int j = 0; j < side; ++j) {
+                    const int n = i * side + j;
+                    if (!real[n]) continue;
+                    for (int dir = 0; dir < 2; ++dir) {
+                        const int ii = i + (dir == 0), jj = j + (dir == 1);
+                        if (ii >= side || jj >= side || !real[ii * side + jj]) continue;
+                        const int q = ii * side + jj;
+                        double d2 = 0;
+                        for (int k = 0; k < 3; ++k) d2 += (mu[3 * n + k] - mu[3 * q + k]) * (mu[3 * n + k] - mu[3 * q + k]);
+                        const double dc = std::max(std::fabs(chb[n] - chb[q]), std::fabs(cox[n] - cox[q]));
+                        index[sidx] = std::max(index[sidx], d2 * dc);
+                    }
+                }
             float blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
             // chunks
             for (int ca = 0; ca < cps; ++ca)
                 for (int cs = 0; cs < cps; ++cs) {
                     float *C = T + kSupHdr + kMaxProbes * kProbeFloats + (size_t)(ca * cps + cs) * kChunkFloats;
+                    float *LO = &lo[((size_t)sidx * cps * cps + (size_t)(ca * cps + cs)) * kLoFloats];
                     float clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
                     for (int j = 0; j < kChunkNodes; ++j) {
                         const int n = (4 * ca + j / 4) * side + 4 * cs + j % 4;
@@ -253,6 +281,7 @@ double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const doubl
                         for (int k = 0; k < 3; ++k) {
                             const float v = (float)rel(n, k);
                             C[16 * k + j] = v;
+                            LO[16 * k + j] = (float)(rel(n, k) - (double)v);
                             sq += (double)v * (double)v;
                             clo[k] = std::min(clo[k], v);
                             chi[k] = std::max(chi[k], v);
@@ -323,6 +352,7 @@ double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const doubl
     for (unsigned i = 0; i < nt; ++i)
         th.emplace_back(work, (int)((long long)n_sup * i / nt), (int)((long long)n_sup * (i + 1) / nt));
     for (auto &x : th) x.join();
+    direct_index = *std::max_element(index.begin(), index.end());
     return *std::max_element(radius.begin(), radius.end());
 }
 
@@ -469,6 +499,7 @@ hb_status_t estimate(hb_plan_s *p, const void *d_frames, int32_t n_frames, const
         pa.scale = p->scale;
         pa.skip_log2 = p->skip_log2;
         pa.part = cb.part;
+        pa.lo = p->precise ? p->d_lo : nullptr;
         pa.work = ev ? p->d_work : nullptr;
         if (ev) p->full_pairs += (long long)n_frames * p->dims.LL * p->n_nodes;
         if (cb.gref) {
@@ -607,6 +638,8 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_tiles, sizeof(float) * (size_t)p->n_tiles * super_floats(p->side));
     if (st == HB_OK)
         st = dev_alloc(p, &p->d_split, (size_t)kSplitChunkBytes * p->n_tiles * (p->side / 4) * (p->side / 4));
+    if (st == HB_OK)
+        st = dev_alloc(p, (void **)&p->d_lo, sizeof(float) * kLoFloats * p->n_tiles * (p->side / 4) * (p->side / 4));
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_z, sizeof(float) * nb * 6 * LL);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_det, sizeof(float2) * nb * HW);
     if (st == HB_OK && desc->lowpass == HB_LOWPASS_BAYES)
@@ -729,18 +762,23 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
     if (hipMemcpy(p->d_mf + 6, mf_extra, sizeof(mf_extra), hipMemcpyHostToDevice) != hipSuccess)
         return HB_ERR_DEVICE;
 
-    std::vector<float> tiles;
-    p->radius = build_supers(d, model, r, (double)p->scale, p->side, tiles);
+    std::vector<float> tiles, lo;
+    double direct_index = 0.0;
+    p->radius = build_supers(d, model, r, (double)p->scale, p->side, tiles, lo, direct_index);
     const double h_thb = d.grid_thb > 1 ? (d.thb_max - d.thb_min) / (d.grid_thb - 1) : 0.0;
     const double h_so2 = d.grid_so2 > 1 ? d.thb_max * (d.so2_max - d.so2_min) / (d.grid_so2 - 1) : 0.0;
     p->info.mfma_index = p->radius * p->radius * std::max(h_thb, h_so2);
     p->use_mfma = p->info.mfma_index <= kMfmaPrecisionBudget;
-    p->info.posterior_kernel = p->use_mfma ? 0 : 1;
+    p->info.direct_index = direct_index;
+    p->precise = !p->use_mfma && direct_index > kDirectPrecisionBudget;
+    p->info.posterior_kernel = p->use_mfma ? 0 : (p->precise ? 2 : 1);
     // Exact skipping (T = kExactSkipLog2) has no error.
     p->info.skip_bound = (p->skip_log2 < kExactSkipLog2)
                              ? 2.0 * (double)p->n_nodes * std::exp2(-(double)p->skip_log2) * d.thb_max
                              : 0.0;
     if (hipMemcpy(p->d_tiles, tiles.data(), sizeof(float) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return HB_ERR_DEVICE;
+    if (hipMemcpy(p->d_lo, lo.data(), sizeof(float) * lo.size(), hipMemcpyHostToDevice) != hipSuccess)
         return HB_ERR_DEVICE;
     std::vector<uint16_t> split_ops;
     build_split_ops(tiles, p->n_tiles, p->side, split_ops);

@@ -79,7 +79,7 @@ class hb_plan_info_t(ctypes.Structure):
                 ("mu_ref", ctypes.c_double * 3), ("grid_split", ctypes.c_int32),
                 ("n_tiles", ctypes.c_int32), ("posterior_kernel", ctypes.c_int32),
                 ("n_nodes", ctypes.c_int64), ("skip_log2", ctypes.c_double), ("skip_bound", ctypes.c_double),
-                ("mfma_index", ctypes.c_double)]
+                ("mfma_index", ctypes.c_double), ("direct_index", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -181,8 +181,9 @@ def hb_plan_get_info(plan: int) -> Dict[str, object]:
     return dict(E=np.array(info.E[:]).reshape(3, 2), M=np.array(info.M[:]).reshape(2, 3),
                 gamma=info.gamma, ref=(info.ref_hb, info.ref_hbo2), mu_ref=np.array(info.mu_ref[:]),
                 grid_split=info.grid_split, n_tiles=info.n_tiles, n_nodes=info.n_nodes,
-                posterior_kernel=("mfma", "direct")[info.posterior_kernel],
-                skip_log2=info.skip_log2, skip_bound=info.skip_bound, mfma_index=info.mfma_index)
+                posterior_kernel=("mfma", "direct", "direct_precise")[info.posterior_kernel],
+                skip_log2=info.skip_log2, skip_bound=info.skip_bound, mfma_index=info.mfma_index,
+                direct_index=info.direct_index)
 
 
 def hb_plan_set_timing(plan: int, enable: bool) -> None:

@@ -59,10 +59,13 @@ int main() {
             const int n_sup = nsa * nss;
             double mu_ref[3];
             fm.mu(50.0, 70.0, mu_ref);
-            std::vector<float> table;
-            const double radius = build_supers(d, fm, mu_ref, 40.0, side, table);
+            std::vector<float> table, lo;
+            double direct_index = -1.0;
+            const double radius = build_supers(d, fm, mu_ref, 40.0, side, table, lo, direct_index);
             if (!(radius >= 0.0) || table.size() != (size_t)n_sup * super_floats(side))
                 return fail("table size or radius", g[0], g[1]);
+            if (lo.size() != (size_t)n_sup * (side / 4) * (side / 4) * kLoFloats || !(direct_index >= 0.0))
+                return fail("low parts or direct index", g[0], g[1]);
             std::vector<uint16_t> ops;
             build_split_ops(table, n_sup, side, ops);
             const int cps = (side / 4) * (side / 4);
@@ -78,6 +81,11 @@ int main() {
                     const uint16_t *O = &ops[((size_t)si * cps + c) * 64 * (kSplitLaneBytes / 2)];
                     for (int j = 0; j < kChunkNodes; ++j) {
                         real += C[48 + j] != kPadLogit;
+                        const float *LO = &lo[((size_t)si * cps + c) * kLoFloats];
+                        for (int k = 0; k < 3; ++k)
+                            if (C[48 + j] != kPadLogit && !(std::fabs(LO[16 * k + j]) <=
+                                                             std::fabs(C[16 * k + j]) * 6.0e-8f + 1e-30f))
+                                return fail("low part larger than half an ulp", si, c);
                         for (int gi = 0; gi < 4; ++gi) {
                             const uint16_t *L = O + (size_t)(16 * gi + j) * (kSplitLaneBytes / 2);
                             // parts 1, 2, 3 sit in slots 0, 1, 3 for coordinates and 0, 1, 2 for the norm

@@ -215,7 +215,7 @@ def test_null_maps_are_skipped(torch_cuda):
 
 @pytest.mark.parametrize("grid,sigma,kernel", [(256, 0.01, "mfma"), (128, 0.01, "mfma"), (512, 0.01, "mfma"),
                                                (64, 0.01, "mfma"), (32, 0.01, "mfma"), (16, 0.01, "direct"),
-                                               (48, 0.001, "direct"), (256, 0.005, "mfma"),
+                                               (48, 0.001, "direct_precise"), (256, 0.005, "mfma"),
                                                (256, 0.004, "direct"), (128, 0.005, "direct")])
 def test_posterior_kernel_choice(torch_cuda, grid, sigma, kernel):
     """Fine grids take the MFMA kernel, grids too coarse for its expanded
@@ -669,8 +669,41 @@ def test_other_forward_models_both_kernels(torch_cuda, camera):
         run.close()
         ora = hbtest.run_oracle(fr[None], "f32", s, sp=sp)
         err = hbtest.assert_maps_close(gpu, ora, f"{camera} grid {grid} sigma {sigma}")
-        assert info["posterior_kernel"] == ("mfma" if info["mfma_index"] <= 700 else "direct")
+        assert info["posterior_kernel"] == ("mfma" if info["mfma_index"] <= 700 else
+                                            "direct_precise" if info["direct_index"] > 3800 else "direct")
         kernels.add(info["posterior_kernel"])
         print(camera, grid, sigma, f"R2h={info['mfma_index']:.0f}", info["posterior_kernel"],
               {k: f"{v:.2e}" for k, v in err.items()})
-    assert kernels == {"mfma", "direct"}
+    assert "mfma" in kernels and kernels & {"direct", "direct_precise"}
+
+
+# Grids whose neighbouring nodes are far apart in the likelihood's units:
+# (thb range, so2 range, grid_thb, grid_so2, sigma, camera).  The first is a
+# case a float32 difference form misses by 1.4e-4 uM (four THb nodes 68 uM
+# apart, a pixel between two of them).
+COARSE_CASES = [
+    ((19.9067, 224.7241), (0.36469, 0.87482), 4, 25, 0.02, "shifted"),
+    ((20.0, 200.0), (0.3, 1.0), 32, 32, 0.001, "default"),
+    ((20.0, 200.0), (0.3, 1.0), 2, 2, 0.015, "default"),
+    ((20.0, 200.0), (0.3, 1.0), 6, 58, 0.006, "default"),
+]
+
+
+@pytest.mark.parametrize("thb,so2,gt,gs,sigma,camera", COARSE_CASES)
+def test_coarse_grids_take_double_float_logits(torch_cuda, thb, so2, gt, gs, sigma, camera):
+    """Plans whose direct index (squared scaled distance between neighbouring
+    nodes times their Hb/HbO2 difference) exceeds 3800 form the direct
+    kernel's logits from double-float differences and stay within the FP32
+    tolerance of the oracle."""
+    sp = synth.spectra() if camera == "default" else synth.alt_spectra(camera)
+    fr = np.stack([synth.single_frame(30, 96, config=90, stream=31, frame=i, sp=sp)[0] for i in range(3)])
+    s = _settings(levels=1, grid=gt, grid_so2=gs, sigma=sigma, thb_min=thb[0], thb_max=thb[1],
+                  so2_min=so2[0], so2_max=so2[1])
+    run = hbtest.GpuRun(96, 30, s, max_batch=3, sp=sp)
+    info = run.plan.info()
+    assert info["direct_index"] > 3800 and info["posterior_kernel"] == "direct_precise", info
+    gpu = run(fr)
+    run.close()
+    err = hbtest.assert_maps_close(gpu, hbtest.run_oracle(fr, "f32", s, sp=sp), f"coarse G{gt}x{gs} sigma {sigma}")
+    print(f"G{gt}x{gs} sigma {sigma} {camera}: direct index {info['direct_index']:.0f}",
+          {k: f"{v:.2e}" for k, v in err.items()})

@@ -108,3 +108,39 @@ def test_noalloc_refuses_calls_beyond_the_scratch(torch_cuda):
         plan.estimate(d, maps)                                   # the plan's own scratch still works
         torch.cuda.synchronize()
         assert all(torch.isfinite(m[:, :8, :8]).all().item() for m in maps[:3])
+
+
+def test_noalloc_inside_a_captured_graph(torch_cuda):
+    """The call's use case: captured into a HIP graph (nothing to allocate
+    during capture), then replayed on new inputs with eager work between the
+    replays; every replay equals the eager call on the same frames."""
+    torch = torch_cuda
+    from paper_1706_07263_amd import hb
+    h, w = 192, 256
+    print("noalloc graph case 256x192 L2 G64, batch 2", flush=True)
+    desc = hb.make_desc(w, h, levels=2, max_batch=2, grid_thb=64, grid_so2=64)
+    sets = [np.ascontiguousarray(_frames(2, h, w, seed_stream=40 + k)) for k in range(3)]
+    with hb.Plan(desc, 0) as plan:
+        plan.set_forward_model(synth.spectra())
+        stream = torch.cuda.Stream()
+        inp = torch.zeros((2, h, w, 3), device="cuda", dtype=torch.float32)
+        out = _maps(torch, 2, h, w)
+        with torch.cuda.stream(stream):
+            plan.estimate(inp, out, stream, noalloc=True)      # warm-up outside the capture
+        stream.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            plan.estimate(inp, out, stream, noalloc=True)
+        stream.synchronize()
+        for k in (0, 1, 2, 0):
+            inp.copy_(torch.from_numpy(sets[k]))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            got = np.stack([m.cpu().numpy() for m in out], 1)
+            ref = _maps(torch, 2, h, w)
+            plan.estimate(torch.from_numpy(sets[k]).cuda(), ref)    # eager, the plan's own scratch
+            torch.cuda.synchronize()
+            want = np.stack([m.cpu().numpy() for m in ref], 1)
+            assert np.array_equal(got, want, equal_nan=True), f"replay of set {k}"
+        del g
