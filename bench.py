@@ -620,6 +620,7 @@ def main():
     if "modes" in legs:
         modes = posterior_modes(a, hb, torch, synth, frames, maps, stream, mix_rate)
         modes["default"] = {"posterior_tolerance_um": 1e-6, "skip_log2": info["skip_log2"],
+                            "band_log2": info["band_log2"], "band_chunks_per_wave": info["band_chunks"],
                             "skip_bound_um": info["skip_bound"], "frames_per_s": round(fps, 2),
                             "call_ms": round(per[3], 4), "posterior_ms": round(per[1], 4),
                             "evaluated_fraction": roofline["evaluated_fraction"],
@@ -692,6 +693,7 @@ def main():
                    "grid": f"{a.grid}x{a.grid}", "grid_split": info["grid_split"],
                    "posterior_kernel": info["posterior_kernel"],
                    "posterior_tolerance_um": 1e-6, "skip_log2": info["skip_log2"],
+                   "band_log2": info["band_log2"], "band_chunks_per_wave": info["band_chunks"],
                    "parallelism": "1 GPU"},
         "mpixel_per_s": round(fps * H * W / 1e6, 2),
         "stages_ms_per_call": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stage.items()},

@@ -88,10 +88,13 @@ typedef struct {
                                    affects HB_LOWPASS_BAYES; any other value is rejected. */
     double posterior_tolerance; /* uM, finite.  > 0: the posterior skips 4x4-node grid chunks
                                    whose weights are all provably below 2^-T of the pixel's
-                                   reference weight, with T chosen so that the skipped
-                                   weights move the posterior mean of Hb and HbO2 by at
-                                   most this much (bound: 2 G 2^-T thb_max, G grid nodes;
-                                   the T in use is reported by hb_plan_get_info).
+                                   reference weight and, up to a per-wave budget of B
+                                   chunks, chunks below 2^-(T-6), with T and B chosen so
+                                   that the skipped weights move the posterior mean of Hb
+                                   and HbO2 by at most this much (bound: 2 thb_max (G 2^-T
+                                   + 16 B S 2^-(T-6)), G grid nodes, S grid splits;
+                                   T = ceil(log2(2 G thb_max / tolerance)) + 1; T, B and
+                                   the bound are reported by hb_plan_get_info).
                                    0: skip only chunks whose float32 weights are all exactly
                                    zero (T = 160; results equal those of no skipping, bit
                                    for bit).  < 0: skip nothing (every chunk that holds a
@@ -137,6 +140,10 @@ typedef struct {
     double direct_index;  /* max over neighbouring grid nodes of their squared scaled distance times their
                              largest Hb/HbO2 difference (uM); float32 logits can move a posterior mean by
                              about 8e-9 times this                                                        */
+    double band_log2;     /* chunks whose logit bound lies between band_log2 and skip_log2 below the
+                             reference are skipped too, up to band_chunks of them per wave (a wave
+                             covers 32 or 64 pixels); band_log2 = skip_log2: no such budget            */
+    int64_t band_chunks;
 } hb_plan_info_t;
 
 /* Fill `desc` with defaults: 64x64, 1 level, FP32, max_batch 1, grid 128x128

@@ -26,7 +26,8 @@ namespace hb {
 //     [48 + j]: minus the squared norm of the relative coordinates of node j
 //     Slots outside the grid hold kPadCoord coordinates and kPadLogit here.
 //     [64 + j]: Hb of node j minus header[6]     [80 + j]: HbO2 minus header[7]
-//     [96..98] chunk box lower corner, [99..101] upper corner (relative)
+//     [96..98] chunk box lower corner, [99..101] upper corner (absolute:
+//       centre plus the stored coordinates, rounded outward)
 //     [104 + 4 a + (0..3)], a = 0..3: for the chunk row of THb offset a,
 //       Hb = A_h + B_h s at SO2 offset s = 0..3 relative to header[6] (exact
 //       on a product grid: THb is constant along the row and SO2 is linear
@@ -85,6 +86,18 @@ constexpr int kLoFloats = 48;
 // thb_max for G grid nodes.
 constexpr float kExactSkipLog2 = 160.0f;
 constexpr float kMinSkipLog2 = 16.0f;
+// Budgeted skipping below a tolerance-derived threshold.  The hard threshold
+// is T + 1, which spends at most half of the tolerance on G 2^-(T+1); a wave
+// may also leave out chunks bounded between kBandLog2 and T + 1 below its
+// reference, each of whose weights sum to at most 16 2^-(T+1-kBandLog2), as
+// long as its count of such chunks stays within the budget the rest of the
+// tolerance buys (every pixel of the wave then loses at most that mass).
+constexpr float kBandLog2 = 6.0f;
+struct SkipRule {
+    float skip_log2 = kExactSkipLog2, band_log2 = kExactSkipLog2;
+    int band_chunks = 0;
+    double bound = 0.0;   // uM, stated bound on the posterior-mean change
+};
 constexpr int kChunkNodes = 16;
 constexpr int kSupHdr = 32;
 constexpr int kMaxProbes = 16;
@@ -157,6 +170,8 @@ struct PosteriorArgs {
     int split;
     float scale;             // sqrt(log2(e) / (2 sigma^2))
     float skip_log2;         // chunks bounded more than this below the reference are skipped
+    float band_log2;         // chunks bounded more than this below it are skipped while the budget lasts
+    int band_chunks;         // budget: chunks a wave may skip between band_log2 and skip_log2
     float *gref;             // [n][LL] best probe logit over the whole grid, or null (one split)
     float *part;             // [n][split][kPartFields][LL]
     const float *lo;         // direct kernel: [chunk][kLoFloats] coordinate low parts for

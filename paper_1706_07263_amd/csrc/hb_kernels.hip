@@ -80,6 +80,8 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x3 __attribute__((ext_vector_type(3)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 // Word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format).
 constexpr int kBufferWord3 = 0x00020000;
 
@@ -639,28 +641,31 @@ __device__ __forceinline__ f32x4 mfma_16x16x32_bf16(bf16x8 a, bf16x8 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// Nearest bf16 (ties to even) of lo and hi, packed (lo in the low half).
+__device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
+    const f32x2 v = {lo, hi};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+}
+
 // Pixel (B) operand of the split bf16 MFMA.  Lane groups 0..2 carry the
 // exact three-part split of u (twice the pixel's coordinate) in the order
 // that pairs with the node parts of the split operand table; group 3 carries
 // ones that pick up the node's squared-norm parts and the three parts of the
-// pixel's constant c = -(|r|^2 + m), paired with node ones.
+// pixel's constant c = -(|r|^2 + m), paired with node ones.  The parts are
+// x1 = bf16(x), x2 = bf16(x - x1), x3 = bf16(x - x1 - x2), each difference
+// exact in float32.
 __device__ __forceinline__ bf16x8 split_pixel_operand(float u, float c, bool coord) {
     const float x = coord ? u : c;
-    const __bf16 x1 = (__bf16)x;
-    const float r1 = x - (float)x1;
-    const __bf16 x2 = (__bf16)r1;
-    const __bf16 x3 = (__bf16)(r1 - (float)x2);
-    const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
-    bf16x8 b;
-    b[0] = coord ? x1 : one;
-    b[1] = coord ? x1 : one;
-    b[2] = coord ? x2 : one;
-    b[3] = x1;
-    b[4] = x2;
-    b[5] = x3;
-    b[6] = coord ? x2 : zero;
-    b[7] = coord ? x3 : zero;
-    return b;
+    const unsigned p11 = pack_bf16(x, x);                        // (x1, x1)
+    const float r1 = x - __uint_as_float(p11 << 16);             // x - x1, exact
+    const float r2 = r1 - __uint_as_float(pack_bf16(r1, r1) << 16);   // r1 - x2, exact
+    const unsigned p23 = pack_bf16(r1, r2);                      // (x2, x3)
+    u32x4 b;
+    b[0] = coord ? p11 : 0x3f803f80u;                            // (x1, x1) or (1, 1)
+    b[1] = pack_bf16(coord ? r1 : 1.0f, x);                      // (x2, x1) or (1, x1)
+    b[2] = p23;                                                  // (x2, x3)
+    b[3] = coord ? p23 : 0u;                                     // (x2, x3) or (0, 0)
+    return __builtin_bit_cast(bf16x8, b);
 }
 
 constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
@@ -754,6 +759,24 @@ __device__ __forceinline__ float box_box_bound(const float *box, const float r[6
     const float e1 = fmaxf(fmaxf(box[1] - r[4], r[1] - box[4]), 0.0f);
     const float e2 = fmaxf(fmaxf(box[2] - r[5], r[2] - box[5]), 0.0f);
     return -fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+}
+
+// Chunks a wave evaluates, from v = its logit bound minus the wave's
+// reference (one chunk per lane, the lanes of real chunks set in
+// lane_mask): every chunk with v > nband, and those with nskip < v <= nband
+// unless the wave's remaining budget band_left (wave-uniform) covers all of
+// them, which it then shrinks by their count.  With nband == nskip no budget
+// is in use.
+__device__ __forceinline__ unsigned long long kept_chunks(unsigned long long lane_mask, float v, float nskip,
+                                                          float nband, int &band_left) {
+    const unsigned long long keep = __builtin_amdgcn_ballot_w64(v > nband) & lane_mask;
+    const unsigned long long any = __builtin_amdgcn_ballot_w64(v > nskip) & lane_mask;
+    const int nb = __popcll(any & ~keep);
+    if (nb <= band_left) {
+        band_left -= nb;
+        return keep;
+    }
+    return any;
 }
 
 // Widening of the wave's observation box for rounding (scaled units).
@@ -959,6 +982,7 @@ __device__ float far_gap_max(const PosteriorArgs &a, const WaveWork &w, const fl
                              int part, const float zlo[3], const float zhi[3], float mmin, float cur) {
     const int lane = threadIdx.x & 63;
     const float nskip = -a.skip_log2;
+    const float zbox[6] = {zlo[0], zlo[1], zlo[2], zhi[0], zhi[1], zhi[2]};
     float mx = cur;
     for (int g = w.s0; g < w.s1; g += 64) {
         float rbox[6];
@@ -968,14 +992,13 @@ __device__ float far_gap_max(const PosteriorArgs &a, const WaveWork &w, const fl
             const int si = g + __builtin_ctzll(smask);
             smask &= smask - 1;
             const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
-            wave_super_bound(a, si, zlo, zhi, rbox);
             float r[3];
             recentre(T, ph, pl, r);
             const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
             for (int cg = 0; cg < a.chunks_per_super; cg += 64) {
                 const int ct = min(cg + lane, a.chunks_per_super - 1);
                 unsigned long long mask = __ballot(cg + lane < a.chunks_per_super &&
-                                                   box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > nskip);
+                                                   box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, zbox) - mmin > nskip);
                 while (mask) {
                     const float *__restrict__ C = C0 + (size_t)(cg + __builtin_ctzll(mask)) * kChunkFloats;
                     mask &= mask - 1;
@@ -1079,10 +1102,12 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
     // Skipping.  A chunk (or super-tile) whose logit upper bound lies more
     // than skip_log2 below every pixel's reference has every weight below
     // 2^-skip_log2 (exactly 0 in float32 at kExactSkipLog2, so then leaving
-    // it out changes no bit).  The bound is taken between the chunk's box and
-    // the box of the wave's observations (min reference over the wave), one
-    // chunk per lane.
-    const float nskip = -a.skip_log2;
+    // it out changes no bit); chunks between band_log2 and skip_log2 below it
+    // are left out while the wave's budget lasts.  The bound is taken between
+    // the chunk's box and the box of the wave's observations (min reference
+    // over the wave), one chunk per lane.
+    const float nskip = -a.skip_log2, nband = -a.band_log2;
+    int band_left = a.band_chunks;
     float mmin = ref.m;
     if (a.gref) {
         long long p;
@@ -1133,7 +1158,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
         const_cast<float *>(a.supers), (short)0, a.n_supers * a.super_stride * 4, kBufferWord3);
     // A super-tile holds at most 64 chunks (side <= 32): one chunk per lane.
     const int ct = min(lane, a.chunks_per_super - 1);
-    const bool chunk_lane = lane < a.chunks_per_super;
+    const unsigned long long chunk_lanes =
+        a.chunks_per_super >= 64 ? ~0ull : (1ull << a.chunks_per_super) - 1;
+    const float zbox[6] = {zlo[0], zlo[1], zlo[2], zhi[0], zhi[1], zhi[2]};
     // Super-tiles are tested one per lane; the kept ones are walked in order.
     for (int g = w.s0; g < w.s1; g += 64) {
       float rbox[6];
@@ -1144,10 +1171,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
         smask &= smask - 1;
         const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
         const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
-        // chunk tests, one chunk per lane
-        wave_super_bound(a, si, zlo, zhi, rbox);
-        const unsigned long long mask =
-            __ballot(chunk_lane && box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > nskip);
+        // chunk tests, one chunk per lane (absolute boxes)
+        const unsigned long long mask = kept_chunks(
+            chunk_lanes, box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, zbox) - mmin, nskip, nband, band_left);
         if (mask == 0) continue;
         const int kk = lk < 3 ? lk : 0;
         const float ch = T[kk], cl = T[3 + kk];
@@ -1162,8 +1188,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
             av[b] = split_pixel_operand(2.0f * r, -a2, lk < 3);
         }
         float L0[PB], L1[PB], L2[PB];
-#pragma unroll
-        for (int b = 0; b < PB; ++b) L0[b] = L1[b] = L2[b] = 0.0f;
         const int s_first = si * a.chunks_per_super;   // first chunk of the super-tile in the split table
         // byte offset of the first chunk's row coefficients in the super-tile table
         const int c_first = (si * a.super_stride + kSupHdr + kMaxProbes * kProbeFloats + 104) * 4;
@@ -1191,7 +1215,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
         // W0 and first moment W1 = sum s w_s give the row's Hb moment
         // through the affine row coefficients, and W0 its THb moment (THb
         // is constant along the row); HbO2 = THb - Hb after the super-tile.
-        auto eval = [&](const bf16x8 &bv, const f32x3 &qm) {
+        // The first chunk of the super-tile starts the sums.
+        auto eval = [&](const bf16x8 &bv, const f32x3 &qm, auto first) {
             ++executed;
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
@@ -1200,21 +1225,31 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
                 const float w2 = __builtin_amdgcn_exp2f(d[2]), w3 = __builtin_amdgcn_exp2f(d[3]);
                 const float W0 = (w0 + w1) + (w2 + w3);
                 const float W1 = fmaf(3.0f, w3, fmaf(2.0f, w2, w1));
-                L0[b] += W0;
-                L1[b] = fmaf(qm.x, W0, fmaf(qm.y, W1, L1[b]));
-                L2[b] = fmaf(qm.z, W0, L2[b]);
+                if constexpr (decltype(first)::value) {
+                    L0[b] = W0;
+                    L1[b] = fmaf(qm.x, W0, qm.y * W1);
+                    L2[b] = qm.z * W0;
+                } else {
+                    L0[b] += W0;
+                    L1[b] = fmaf(qm.x, W0, fmaf(qm.y, W1, L1[b]));
+                    L2[b] = fmaf(qm.z, W0, L2[b]);
+                }
             }
         };
+        using First = std::true_type;
+        using Next = std::false_type;
+        // The mask holds at least one chunk: the first take gets it.
         bf16x8 bA, bB;
         f32x3 qA, qB;
         take(bA, qA);
-        while (true) {
-            const bool gotB = take(bB, qB);
-            eval(bA, qA);
-            if (!gotB) break;
+        bool more = take(bB, qB);
+        eval(bA, qA, First{});
+        while (more) {
             const bool gotA = take(bA, qA);
-            eval(bB, qB);
+            eval(bB, qB, Next{});
             if (!gotA) break;
+            more = take(bB, qB);
+            eval(bA, qA, Next{});
         }
         const float chb = T[6], cox = T[7];
 #pragma unroll
@@ -1306,7 +1341,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
     float zlo[3], zhi[3];
     wave_obs_box(ph, pl, zlo, zhi);
     PixelRef ref = pixel_reference<PW, 1>(a, w, ph, pl, 0, zlo, zhi);
-    const float nskip = -a.skip_log2;
+    const float nskip = -a.skip_log2, nband = -a.band_log2;
+    int band_left = a.band_chunks;
     float mmin = ref.m;
     if (a.gref) mmin = fmaxf(mmin, a.gref[(size_t)w.f * a.LL + p]);
     if (!(mmin > -INFINITY)) mmin = INFINITY;  // NaN observation: see the MFMA kernel
@@ -1314,6 +1350,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
     for (int o = 32; o >= 1; o >>= 1) mmin = fminf(mmin, __shfl_xor(mmin, o));
     if (__any(!(ref.mup - ref.m <= kFarGap))) ref.m = far_gap_max<PW, 1>(a, w, ph, pl, 0, zlo, zhi, mmin, ref.m);
     const float nm = -ref.m;
+    const float zbox[6] = {zlo[0], zlo[1], zlo[2], zhi[0], zhi[1], zhi[2]};
     float R0 = 0.f, R1 = 0.f, R2 = 0.f, K0 = 0.f, K1 = 0.f, K2 = 0.f;
     unsigned executed = 0;
     for (int g = w.s0; g < w.s1; g += 64) {
@@ -1324,7 +1361,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
             const int si = g + __builtin_ctzll(smask);
             smask &= smask - 1;
             const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
-            wave_super_bound(a, si, zlo, zhi, rbox);
             float r[3], rh[3], rl[3];
             if (PRECISE) {
 #pragma unroll
@@ -1340,8 +1376,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
             const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
             for (int cg = 0; cg < a.chunks_per_super; cg += 64) {
                 const int ct = min(cg + lane, a.chunks_per_super - 1);
-                unsigned long long mask = __ballot(cg + lane < a.chunks_per_super &&
-                                                   box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, rbox) - mmin > nskip);
+                const int nc = a.chunks_per_super - cg;
+                unsigned long long mask =
+                    kept_chunks(nc >= 64 ? ~0ull : (1ull << nc) - 1,
+                                box_box_bound(C0 + (size_t)ct * kChunkFloats + 96, zbox) - mmin, nskip, nband, band_left);
                 while (mask) {
                     const int ci = cg + __builtin_ctzll(mask);
                     const float *__restrict__ C = C0 + (size_t)ci * kChunkFloats;

@@ -56,6 +56,8 @@ struct hb_plan_s {
     float iref[3] = {1, 1, 1};
     float scale = 1.0f;
     float skip_log2 = kExactSkipLog2;
+    float band_log2 = kExactSkipLog2;   // = skip_log2 when no budget is in use
+    int band_chunks = 0;
 
     hipEvent_t done = nullptr;       // recorded after each uncaptured hb_estimate_frames
     bool timing = false;
@@ -110,6 +112,37 @@ Dims make_dims(const hb_plan_desc_t &d) {
     m.bps = std::max(1, kStripPixels >> (2 * d.levels));
     m.strips_per_row = (m.wl + m.bps - 1) / m.bps;
     return m;
+}
+
+// Skip thresholds and band budget for a posterior tolerance tol (uM) on a
+// grid of G nodes with THb up to thb_max, seen by `split` grid splits.
+// tol > 0: T = the smallest threshold with 2 G 2^-T thb_max <= tol; skip hard
+// at T + 1 (at most half of tol) and spend the rest on a per-wave budget of
+// chunks bounded between T + 1 and T + 1 - kBandLog2 (each at most 16 nodes
+// of weight 2^-(T + 1 - kBandLog2)), shared out between the splits.  At the
+// exact threshold (T reaching kExactSkipLog2) there is no band and no error.
+// tol == 0: exact skipping.  tol < 0: no skipping.
+SkipRule skip_rule(double G, double thb_max, double tol, int split) {
+    SkipRule r;
+    if (tol > 0) {
+        const double t = std::ceil(std::log2(2.0 * G * thb_max / tol));
+        r.skip_log2 = (float)std::min<double>(kExactSkipLog2, std::max<double>(kMinSkipLog2, t));
+        r.band_log2 = r.skip_log2;
+        if (r.skip_log2 + 1.0f < kExactSkipLog2) {
+            r.skip_log2 += 1.0f;
+            r.band_log2 = r.skip_log2 - kBandLog2;
+            const double hard = 2.0 * G * std::exp2(-(double)r.skip_log2) * thb_max;
+            const double per_chunk = 2.0 * kChunkNodes * std::exp2(-(double)r.band_log2) * thb_max;
+            const double n = std::floor((tol - hard) / per_chunk / split);
+            r.band_chunks = (int)std::max(0.0, std::min(n, 1.0e6));
+        }
+        if (r.skip_log2 < kExactSkipLog2)
+            r.bound = 2.0 * G * std::exp2(-(double)r.skip_log2) * thb_max +
+                      2.0 * kChunkNodes * std::exp2(-(double)r.band_log2) * thb_max * (double)r.band_chunks * split;
+    } else if (tol < 0) {
+        r.skip_log2 = r.band_log2 = INFINITY;   // every chunk holding a grid node is evaluated
+    }
+    return r;
 }
 
 int auto_split(const Dims &dm, int n_tiles, int max_batch) {
@@ -177,6 +210,18 @@ struct ForwardModel {
         }
     }
 };
+
+// Largest float <= x and smallest float >= x (infinities stay).
+float float_down(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = std::nextafter(f, -INFINITY);
+    return f;
+}
+float float_up(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = std::nextafter(f, INFINITY);
+    return f;
+}
 
 // Build the super-tile table (FP64 arithmetic, FP32 storage): scaled
 // log-attenuation of every grid node centred on mu_ref, stored relative to its
@@ -269,6 +314,7 @@ double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const doubl
                     float *C = T + kSupHdr + kMaxProbes * kProbeFloats + (size_t)(ca * cps + cs) * kChunkFloats;
                     float *LO = &lo[((size_t)sidx * cps * cps + (size_t)(ca * cps + cs)) * kLoFloats];
                     float clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+                    double alo[3] = {INFINITY, INFINITY, INFINITY}, ahi[3] = {-INFINITY, -INFINITY, -INFINITY};
                     for (int j = 0; j < kChunkNodes; ++j) {
                         const int n = (4 * ca + j / 4) * side + 4 * cs + j % 4;
                         if (!real[n]) {
@@ -285,6 +331,8 @@ double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const doubl
                             sq += (double)v * (double)v;
                             clo[k] = std::min(clo[k], v);
                             chi[k] = std::max(chi[k], v);
+                            alo[k] = std::min(alo[k], cen_d[k] + (double)v);
+                            ahi[k] = std::max(ahi[k], cen_d[k] + (double)v);
                         }
                         C[48 + j] = (float)(-sq);
                         radius[sidx] = std::max(radius[sidx], std::sqrt(sq));
@@ -292,8 +340,9 @@ double build_supers(const hb_plan_desc_t &d, const ForwardModel &fm, const doubl
                         C[80 + j] = (float)(cox[n] - (double)cox_c);
                     }
                     for (int k = 0; k < 3; ++k) {
-                        C[96 + k] = clo[k];
-                        C[99 + k] = chi[k];
+                        // absolute box of the stored nodes, rounded outward
+                        C[96 + k] = float_down(alo[k]);
+                        C[99 + k] = float_up(ahi[k]);
                         blo[k] = std::min(blo[k], clo[k]);
                         bhi[k] = std::max(bhi[k], chi[k]);
                     }
@@ -498,6 +547,8 @@ hb_status_t estimate(hb_plan_s *p, const void *d_frames, int32_t n_frames, const
         pa.split = p->split;
         pa.scale = p->scale;
         pa.skip_log2 = p->skip_log2;
+        pa.band_log2 = p->band_log2;
+        pa.band_chunks = p->band_chunks;
         pa.part = cb.part;
         pa.lo = p->precise ? p->d_lo : nullptr;
         pa.work = ev ? p->d_work : nullptr;
@@ -667,13 +718,14 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     p->info.grid_split = p->split;
     p->info.n_tiles = p->n_tiles;
     p->info.n_nodes = p->n_nodes;
-    if (desc->posterior_tolerance > 0) {
-        const double t = std::ceil(std::log2(2.0 * (double)p->n_nodes * desc->thb_max / desc->posterior_tolerance));
-        p->skip_log2 = (float)std::min<double>(kExactSkipLog2, std::max<double>(kMinSkipLog2, t));
-    } else if (desc->posterior_tolerance < 0) {
-        p->skip_log2 = INFINITY;   // no skipping: every chunk holding a grid node is evaluated
-    }
+    const SkipRule rule = skip_rule((double)p->n_nodes, desc->thb_max, desc->posterior_tolerance, p->split);
+    p->skip_log2 = rule.skip_log2;
+    p->band_log2 = rule.band_log2;
+    p->band_chunks = rule.band_chunks;
+    p->info.skip_bound = rule.bound;
     p->info.skip_log2 = p->skip_log2;
+    p->info.band_log2 = p->band_log2;
+    p->info.band_chunks = p->band_chunks;
     *out = p;
     return HB_OK;
 }
@@ -772,10 +824,6 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
     p->info.direct_index = direct_index;
     p->precise = !p->use_mfma && direct_index > kDirectPrecisionBudget;
     p->info.posterior_kernel = p->use_mfma ? 0 : (p->precise ? 2 : 1);
-    // Exact skipping (T = kExactSkipLog2) has no error.
-    p->info.skip_bound = (p->skip_log2 < kExactSkipLog2)
-                             ? 2.0 * (double)p->n_nodes * std::exp2(-(double)p->skip_log2) * d.thb_max
-                             : 0.0;
     if (hipMemcpy(p->d_tiles, tiles.data(), sizeof(float) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
         return HB_ERR_DEVICE;
     if (hipMemcpy(p->d_lo, lo.data(), sizeof(float) * lo.size(), hipMemcpyHostToDevice) != hipSuccess)

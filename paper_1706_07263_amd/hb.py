@@ -79,7 +79,8 @@ class hb_plan_info_t(ctypes.Structure):
                 ("mu_ref", ctypes.c_double * 3), ("grid_split", ctypes.c_int32),
                 ("n_tiles", ctypes.c_int32), ("posterior_kernel", ctypes.c_int32),
                 ("n_nodes", ctypes.c_int64), ("skip_log2", ctypes.c_double), ("skip_bound", ctypes.c_double),
-                ("mfma_index", ctypes.c_double), ("direct_index", ctypes.c_double)]
+                ("mfma_index", ctypes.c_double), ("direct_index", ctypes.c_double),
+                ("band_log2", ctypes.c_double), ("band_chunks", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -183,7 +184,7 @@ def hb_plan_get_info(plan: int) -> Dict[str, object]:
                 grid_split=info.grid_split, n_tiles=info.n_tiles, n_nodes=info.n_nodes,
                 posterior_kernel=("mfma", "direct", "direct_precise")[info.posterior_kernel],
                 skip_log2=info.skip_log2, skip_bound=info.skip_bound, mfma_index=info.mfma_index,
-                direct_index=info.direct_index)
+                direct_index=info.direct_index, band_log2=info.band_log2, band_chunks=info.band_chunks)
 
 
 def hb_plan_set_timing(plan: int, enable: bool) -> None:

@@ -5,8 +5,10 @@
 // builder directly, for ragged and square grids of every super-tile side,
 // with and without the illumination projection, and checks the layout's
 // invariants on the way: probe counts, padded slots, and that every split
-// operand's three parts add up to its float value exactly.  It also runs
-// the plan's host-side validation (no device is needed for either).  The
+// operand's three parts add up to its float value exactly.  It also checks
+// the skip rule's stated bound against the tolerance over a range of grids
+// and tolerances, and runs the plan's host-side validation (no device is
+// needed for any of this).  The
 // kernel launchers and the static scratch lookup are stubs: nothing here
 // touches a GPU.  Prints "plan tables asan ok" and returns 0 on success.
 #include "hb_plan.cpp"
@@ -98,6 +100,36 @@ int main() {
             }
             if (real != (long)d.grid_thb * d.grid_so2) return fail("real node count", g[0], g[1]);
         }
+    // Skip rule: the stated bound never exceeds the tolerance, the hard
+    // threshold spends at most half of it, and the band sits kBandLog2 above.
+    for (double G : {1.0, 16.0, 1024.0, 65536.0, 1048576.0})
+        for (double thb_max : {100.0, 200.0})
+            for (double tol : {1e-12, 1e-9, 1e-6, 1e-4, 1e-2, 1.0, 1e3})
+                for (int split : {1, 3, 16}) {
+                    const SkipRule r = skip_rule(G, thb_max, tol, split);
+                    const double hard = 2.0 * G * std::exp2(-(double)r.skip_log2) * thb_max;
+                    if (!(r.bound <= tol) || r.band_chunks < 0 || r.skip_log2 < kMinSkipLog2 ||
+                        r.skip_log2 > kExactSkipLog2)
+                        return fail("skip bound above tolerance", (int)G, split);
+                    if (r.skip_log2 < kExactSkipLog2 && !(r.bound >= hard && hard <= 0.5 * tol + 1e-300))
+                        return fail("hard threshold spends more than half", (int)G, split);
+                    if (r.band_chunks > 0 && r.band_log2 != r.skip_log2 - kBandLog2)
+                        return fail("band threshold", (int)G, split);
+                    if (r.band_chunks == 0 && r.skip_log2 < kExactSkipLog2 && r.band_log2 != r.skip_log2 &&
+                        r.band_log2 != r.skip_log2 - kBandLog2)
+                        return fail("band threshold without budget", (int)G, split);
+                }
+    {
+        const SkipRule e = skip_rule(65536.0, 200.0, 0.0, 1), n = skip_rule(65536.0, 200.0, -1.0, 1);
+        const SkipRule d = skip_rule(65536.0, 200.0, 1e-6, 1);
+        if (e.skip_log2 != kExactSkipLog2 || e.band_log2 != kExactSkipLog2 || e.band_chunks || e.bound != 0.0)
+            return fail("exact skipping rule", 0, 0);
+        if (!std::isinf(n.skip_log2) || !std::isinf(n.band_log2) || n.band_chunks || n.bound != 0.0)
+            return fail("no-skipping rule", 0, 0);
+        // 256 x 256 grid, thb_max 200, 1e-6 uM: T = 45, hard at 46, band to 40, 107 chunks
+        if (d.skip_log2 != 46.0f || d.band_log2 != 40.0f || d.band_chunks != 107)
+            return fail("default rule", (int)d.skip_log2, d.band_chunks);
+    }
     // Host-side validation and the no-device path of plan creation.
     hb_plan_desc_t d;
     hb_plan_desc_default(&d);

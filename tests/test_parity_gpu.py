@@ -373,8 +373,11 @@ def test_posterior_tolerance_skips_within_its_bound(torch_cuda, tol):
         if t == 0.0:
             assert info["skip_log2"] == 160.0 and info["skip_bound"] == 0.0
         else:
-            want = math.ceil(math.log2(2 * 256 * 256 * 200.0 / t))
-            assert info["skip_log2"] == min(160, max(16, want))
+            want = min(160, max(16, math.ceil(math.log2(2 * 256 * 256 * 200.0 / t))))
+            # hard threshold one above; the rest of the tolerance buys a budget of
+            # chunks bounded up to six above it
+            assert info["skip_log2"] == want + 1 and info["band_log2"] == want + 1 - 6
+            assert info["band_chunks"] > 0
             assert 0 < info["skip_bound"] <= t
             bound = info["skip_bound"]
         hb.hb_plan_set_timing(run.plan.handle, True)
