@@ -58,8 +58,8 @@ NOMINAL_CEILING_PAIRS_PER_S = 256 * N_SIMD * CLOCK_HZ / CHUNK_BLOCK_CYCLES      
 # rocprofv3 FETCH_SIZE/WRITE_SIZE runs summarised in profiles/, valid for the
 # device sources whose combined sha256 (kernel_source_sha) starts with
 # PROFILED_KERNEL_SHA; reported as null for any other source or workload.
-PROFILED_KERNEL_SHA = "b7ec587d7435c2a8"
-PROFILED_POSTERIOR_TRAFFIC = 1248.96e6
+PROFILED_KERNEL_SHA = "350fd39a163b7700"
+PROFILED_POSTERIOR_TRAFFIC = 1195.16e6
 KERNEL_SOURCES = ("hb_kernels.hip", "hb_internal.h", "hb_df.h")
 
 
