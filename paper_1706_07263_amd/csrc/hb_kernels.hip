@@ -1078,9 +1078,11 @@ __device__ __forceinline__ void fused_maps(const PosteriorArgs &a, const WaveWor
 // nodes of one chunk row (lane l: pixel l % 16, THb row l / 16, SO2 offsets
 // 0..3) and runs the exponentials and the moments on the VALU.
 // Two pixel blocks per wave (an 8 x 4 tile) at six waves per SIMD (80 VGPRs,
-// no spills) measured fastest on the 1080p workload.
-template <int PB>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_posterior(PosteriorArgs a) {
+// no spills) measured fastest on the 1080p workload; WAVES = 4 (87 VGPRs,
+// three operand buffers) serves launches small enough to be resident at
+// once.  Both evaluate the same chunks in the same order.
+template <int PB, int WAVES>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_posterior(PosteriorArgs a) {
     constexpr int PW = 16 * PB;
     constexpr int LPP = 64 / PW;
     const int lane = threadIdx.x & 63;
@@ -1245,17 +1247,38 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6
         using First = std::true_type;
         using Next = std::false_type;
         // The mask holds at least one chunk: the first take gets it.
-        bf16x8 bA, bB;
-        f32x3 qA, qB;
-        take(bA, qA);
-        bool more = take(bB, qB);
-        eval(bA, qA, First{});
-        while (more) {
-            const bool gotA = take(bA, qA);
-            eval(bB, qB, Next{});
-            if (!gotA) break;
-            more = take(bB, qB);
-            eval(bA, qA, Next{});
+        if constexpr (WAVES >= 6) {
+            bf16x8 bA, bB;
+            f32x3 qA, qB;
+            take(bA, qA);
+            bool more = take(bB, qB);
+            eval(bA, qA, First{});
+            while (more) {
+                const bool gotA = take(bA, qA);
+                eval(bB, qB, Next{});
+                if (!gotA) break;
+                more = take(bB, qB);
+                eval(bA, qA, Next{});
+            }
+        } else {
+            // Fewer resident waves hide less latency: three buffers, two
+            // chunks' operands in flight.
+            bf16x8 bA, bB, bC;
+            f32x3 qA, qB, qC;
+            take(bA, qA);
+            bool gotB = take(bB, qB);
+            bool gotC = take(bC, qC);
+            eval(bA, qA, First{});
+            while (gotB) {
+                const bool gotA = take(bA, qA);
+                eval(bB, qB, Next{});
+                if (!gotC) break;
+                gotB = take(bB, qB);
+                eval(bC, qC, Next{});
+                if (!gotA) break;
+                gotC = take(bC, qC);
+                eval(bA, qA, Next{});
+            }
         }
         const float chb = T[6], cox = T[7];
 #pragma unroll
@@ -1543,8 +1566,13 @@ hipError_t launch_posterior(const PosteriorArgs &a, bool mfma, hipStream_t s) {
     const long long per_frame = (long long)((a.wl + kWaveTileW - 1) / kWaveTileW) * ((a.hl + 4 * th - 1) / (4 * th));
     const long long grid = per_frame * a.n_frames * a.split;
     if (grid <= 0) return hipSuccess;
-    if (mfma)
-        hipLaunchKernelGGL(k_posterior<kPixelBlocks>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
+    // A launch whose workgroups are all resident at once runs about four
+    // waves per SIMD: the variant built for four keeps more loads in flight
+    // (same arithmetic, same bits).
+    if (mfma && grid <= kResidentGroups)
+        hipLaunchKernelGGL((k_posterior<kPixelBlocks, 4>), dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
+    else if (mfma)
+        hipLaunchKernelGGL((k_posterior<kPixelBlocks, 6>), dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
     else if (a.lo)
         hipLaunchKernelGGL(k_posterior_direct<true>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
     else

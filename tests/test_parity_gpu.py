@@ -131,6 +131,22 @@ def test_batch_invariance_and_determinism(torch_cuda):
     run.close()
 
 
+def test_small_and_large_launches_agree_bitwise(torch_cuda):
+    """A launch whose workgroups are all resident at once (one 512x512 frame
+    at one level: 512 workgroups) runs the posterior variant built for four
+    waves per SIMD; four frames (2048 workgroups) run the six-wave variant
+    with XCD-contiguous tile order.  Same chunks, same order: same bits."""
+    frames = np.stack([synth.single_frame(512, 512, config=62, stream=20 + i)[0] for i in range(4)])
+    s = _settings(levels=1, grid=128)
+    run = hbtest.GpuRun(512, 512, s, max_batch=4)
+    assert run.plan.info()["posterior_kernel"] == "mfma"
+    every = run(frames)
+    for k in (0, 3):
+        alone = run(frames[k:k + 1])
+        assert np.array_equal(alone[0], every[k], equal_nan=True), k
+    run.close()
+
+
 @pytest.mark.parametrize("dtype", ["f16", "bf16"])
 def test_half_storage_matches_oracle_on_quantised_input(torch_cuda, dtype):
     w = synth.config1(dtype)
