@@ -1078,9 +1078,10 @@ __device__ __forceinline__ void fused_maps(const PosteriorArgs &a, const WaveWor
 // nodes of one chunk row (lane l: pixel l % 16, THb row l / 16, SO2 offsets
 // 0..3) and runs the exponentials and the moments on the VALU.
 // Two pixel blocks per wave (an 8 x 4 tile) at six waves per SIMD (80 VGPRs,
-// no spills) measured fastest on the 1080p workload; WAVES = 4 (87 VGPRs,
-// three operand buffers) serves launches small enough to be resident at
-// once.  Both evaluate the same chunks in the same order.
+// no spills) measured fastest on the 1080p workload; WAVES = 4 (88 VGPRs,
+// three operand buffers, wave priority by predicted work) serves launches
+// small enough to be resident at once.  Both evaluate the same chunks in
+// the same order.
 template <int PB, int WAVES>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_posterior(PosteriorArgs a) {
     constexpr int PW = 16 * PB;
@@ -1174,6 +1175,20 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W
       float rbox[6];
       const int sl = g + lane;
       unsigned long long smask = __ballot(sl < w.s1 && wave_super_bound(a, sl, zlo, zhi, rbox) - mmin > nskip);
+      if constexpr (WAVES < 6) {
+        // All waves of such a launch start together and the launch lasts as
+        // long as its busiest wave, whose work the count of super-tiles it
+        // keeps predicts: busier waves get the SIMD first (scheduling only).
+        // Thresholds at 1/3, 3/8 and 5/12 of the split's super-tiles; on
+        // 1080p frames with a 256^2 grid waves keeping 5/12 or more average
+        // twice the chunks of the median wave.
+        if (g == w.s0) {
+          const int kept = 24 * __popcll(smask), n = w.s1 - w.s0;
+          if (kept >= 10 * n) __builtin_amdgcn_s_setprio(3);
+          else if (kept >= 9 * n) __builtin_amdgcn_s_setprio(2);
+          else if (kept >= 8 * n) __builtin_amdgcn_s_setprio(1);
+        }
+      }
       while (smask) {
         const int si = g + __builtin_ctzll(smask);
         smask &= smask - 1;
