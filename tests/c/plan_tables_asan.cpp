@@ -4,8 +4,9 @@
 // unit and calls the FP64 super-tile table builder and the bf16 split-operand
 // builder directly, for ragged and square grids of every super-tile side,
 // with and without the illumination projection, and checks the layout's
-// invariants on the way: probe counts, padded slots, and that every split
-// operand's three parts add up to its float value exactly.  It also checks
+// invariants on the way: probe counts, padded slots, absolute chunk boxes
+// that hold their nodes, and that every split operand's three parts add up
+// to its float value exactly.  It also checks
 // the skip rule's stated bound against the tolerance over a range of grids
 // and tolerances, and runs the plan's host-side validation (no device is
 // needed for any of this).  The
@@ -83,6 +84,13 @@ int main() {
                     const uint16_t *O = &ops[((size_t)si * cps + c) * 64 * (kSplitLaneBytes / 2)];
                     for (int j = 0; j < kChunkNodes; ++j) {
                         real += C[48 + j] != kPadLogit;
+                        // the absolute chunk box holds the node: centre (double-float) plus
+                        // its stored coordinates, in exact arithmetic
+                        for (int k = 0; k < 3 && C[48 + j] != kPadLogit; ++k) {
+                            const double at = ((double)T[k] + (double)T[3 + k]) + (double)C[16 * k + j];
+                            if (!((double)C[96 + k] <= at && at <= (double)C[99 + k]))
+                                return fail("absolute chunk box misses a node", si, c);
+                        }
                         const float *LO = &lo[((size_t)si * cps + c) * kLoFloats];
                         for (int k = 0; k < 3; ++k)
                             if (C[48 + j] != kPadLogit && !(std::fabs(LO[16 * k + j]) <=
