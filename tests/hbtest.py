@@ -14,7 +14,7 @@ from paper_1706_07263_amd import synth
 # FP32-mode tolerances (uM; SO2 relative to THb), stated for this path.
 TOL_HB = 1e-4
 TOL_THB = 2e-4
-TOL_SO2_NUM = 3e-4     # |dSO2| <= TOL_SO2_NUM / THb where THb >= 1 uM
+TOL_SO2_NUM = 3e-4     # |dSO2| <= TOL_SO2_NUM / THb where THb >= 1 uM and |SO2| <= 1
 
 
 def oracle_model(sp: synth.Spectra) -> orc.Model:
@@ -120,8 +120,14 @@ def assert_maps_close(gpu: np.ndarray, ora: np.ndarray, where: str = "") -> Dict
     thb = o[:, 2]
     sel = fin[:, 3] & (thb >= 1.0)
     e = np.abs(g[:, 3] - o[:, 3])[sel] * thb[sel]
+    # SO2 = HbO2 / THb, so dSO2 * THb = dHbO2 - SO2 * dTHb, within
+    # TOL_HB + |SO2| TOL_THB: TOL_SO2_NUM for SO2 in [0, 1].  Linear
+    # (Tikhonov) low-pass estimates can leave that range where THb is small
+    # next to Hb and HbO2 of opposite signs.
+    lim = np.maximum(TOL_SO2_NUM, TOL_HB + np.abs(o[:, 3][sel]) * TOL_THB)
     err["so2_x_thb"] = float(e.max()) if e.size else 0.0
-    assert err["so2_x_thb"] <= TOL_SO2_NUM, f"{where}: max |dSO2|*THb = {err['so2_x_thb']:.3e}"
+    worst = float((e / lim).max()) if e.size else 0.0
+    assert worst <= 1.0, f"{where}: max |dSO2|*THb = {err['so2_x_thb']:.3e}, {worst:.2f} of its limit"
     return err
 
 

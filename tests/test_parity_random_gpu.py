@@ -12,7 +12,7 @@ from tests import hbtest
 
 pytestmark = pytest.mark.gpu
 
-N_CASES = 36
+N_CASES = 100
 
 
 @pytest.fixture(scope="module")
