@@ -1,6 +1,7 @@
 // Double-float (unevaluated sum of two float32) helpers for the few places
 // where the path needs more than float32 precision without using FP64:
-// the natural log of a ratio of two float32 intensities.
+// the natural log of a ratio of two float32 intensities, sums, and products
+// with a double-float operator.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -47,6 +48,18 @@ HB_HD void df_add2(float &hi, float &lo, float xh, float xl) {
     float s, e;
     two_sum(hi, xh, s, e);
     e += lo + xl;
+    fast_two_sum(s, e, hi, lo);
+}
+
+// (hi, lo) += (mh + ml) (xh + xl), the leading product split exactly by FMA
+// and the cross terms (below the leading one's rounding) added in float32.
+HB_HD void df_mul_add(float &hi, float &lo, float mh, float ml, float xh, float xl) {
+#pragma clang fp contract(off)
+    const float p = mh * xh;
+    const float pe = fmaf(mh, xh, -p);
+    float s, e;
+    two_sum(hi, p, s, e);
+    e += lo + (pe + fmaf(mh, xl, ml * xh));
     fast_two_sum(s, e, hi, lo);
 }
 

@@ -31,7 +31,10 @@ namespace {
 // K0: Jacobian of the forward model at the reference point and the Tikhonov
 // operator, in double precision.  in = [n, L, ref_hb, ref_hbo2, lambda,
 // eps_hb[n], eps_hbo2[n], response[3][n] (rows normalised to unit sum)];
-// out = [E(6), M(6), gamma, ok].
+// out = [E(6), M(6), gamma, ok]; mf[0..5] = M rounded to float32 and
+// mf[8..13] the low parts (M - mf[0..5], rounded), so that mf[i] + mf[8 + i]
+// carries M to double-float precision (mf[6, 7] and mf[14, 15] are the
+// host's low-pass offset).
 // ---------------------------------------------------------------------------
 __global__ void k_tikhonov_fp64(const double *__restrict__ in, double *__restrict__ out,
                                 float *__restrict__ mf) {
@@ -69,6 +72,8 @@ __global__ void k_tikhonov_fp64(const double *__restrict__ in, double *__restric
         out[9 + k] = m1;
         mf[k] = (float)m0;
         mf[3 + k] = (float)m1;
+        mf[8 + k] = (float)(m0 - (double)(float)m0);   // low parts
+        mf[11 + k] = (float)(m1 - (double)(float)m1);
     }
     for (int i = 0; i < 6; ++i) out[i] = E[i];
     out[12] = gamma;
@@ -165,8 +170,15 @@ __device__ __forceinline__ float neg_log_ratio(float I, float R, float rinv) {
 // u equal those of y = -ln I (they differ by a per-block constant); the block
 // mean of y is recovered as -ln(R/I_ref) + mean(u) relative to the plan's
 // reference intensity I_ref.
+//
+// DF (three levels or more): u and the Haar cascade are double-floats (the
+// low parts in s_i once the intensities are used) and the Tikhonov operator
+// is applied with M as a double-float.  With float32 u, the rounding of u,
+// which grows with the block, reaches the maps through |M| (1e3 to 2e3 uM
+// per unit) at up to 1.3e-4 uM for three levels; the double-float form
+// leaves the rounding of the Tikhonov results and of the inverse Haar.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool DF>
 __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict__ frames, HaarArgs a) {
     __shared__ float s_i[3][kStripPixels];
     __shared__ float s_u[3][kStripPixels];
@@ -240,7 +252,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
             for (int c = tid; c < ncols; c += kBlockThreads) {
                 const float I = s_i[k][r * Wt + c];
                 const float R = (n > 0) ? s_r[k][c >> n] : I;
-                s_u[k][r * Wt + c] = neg_log_ratio(I, R, 1.0f / R);
+                if constexpr (DF) {
+                    float uh, ul;
+                    ln_ratio_df(R, I, uh, ul);   // ln(R / I) = -ln(I / R)
+                    s_u[k][r * Wt + c] = uh;
+                    s_i[k][r * Wt + c] = ul;
+                } else {
+                    s_u[k][r * Wt + c] = neg_log_ratio(I, R, 1.0f / R);
+                }
             }
     __syncthreads();
 
@@ -253,12 +272,37 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
             for (int q = tid; q < gc * 3; q += kBlockThreads) {
                 const int cg = q / 3, k = q - 3 * cg, c = cg * g2;
                 float *u = s_u[k];
-                const float w0 = u[r * Wt + c], w1 = u[r * Wt + c + h];
-                const float w2 = u[(r + h) * Wt + c], w3 = u[(r + h) * Wt + c + h];
-                u[r * Wt + c] = 0.5f * ((w0 + w1) + (w2 + w3));
-                u[(r + h) * Wt + c] = 0.5f * ((w0 + w1) - (w2 + w3));
-                u[(r + h) * Wt + c + h] = 0.5f * ((w0 - w1) - (w2 - w3));
-                u[r * Wt + c + h] = 0.5f * ((w0 - w1) + (w2 - w3));
+                const int i0 = r * Wt + c, i1 = i0 + h, i2 = (r + h) * Wt + c, i3 = i2 + h;
+                if constexpr (DF) {
+                    const float *ul = s_i[k];
+                    float ah = u[i0], al = ul[i0], bh = u[i2], bl = ul[i2];
+                    float ch = ah, cl = al, dh = bh, dl = bl;
+                    df_add2(ah, al, u[i1], ul[i1]);     // w0 + w1
+                    df_add2(bh, bl, u[i3], ul[i3]);     // w2 + w3
+                    df_add2(ch, cl, -u[i1], -ul[i1]);   // w0 - w1
+                    df_add2(dh, dl, -u[i3], -ul[i3]);   // w2 - w3
+                    float llh = ah, lll = al, d1h = ah, d1l = al, d2h = ch, d2l = cl, d3h = ch, d3l = cl;
+                    df_add2(llh, lll, bh, bl);
+                    df_add2(d1h, d1l, -bh, -bl);
+                    df_add2(d2h, d2l, -dh, -dl);
+                    df_add2(d3h, d3l, dh, dl);
+                    float *vl = s_i[k];
+                    u[i0] = 0.5f * llh;
+                    vl[i0] = 0.5f * lll;
+                    u[i2] = 0.5f * d1h;
+                    vl[i2] = 0.5f * d1l;
+                    u[i3] = 0.5f * d2h;
+                    vl[i3] = 0.5f * d2l;
+                    u[i1] = 0.5f * d3h;
+                    vl[i1] = 0.5f * d3l;
+                } else {
+                    const float w0 = u[i0], w1 = u[i1];
+                    const float w2 = u[i2], w3 = u[i3];
+                    u[i0] = 0.5f * ((w0 + w1) + (w2 + w3));
+                    u[i2] = 0.5f * ((w0 + w1) - (w2 + w3));
+                    u[i3] = 0.5f * ((w0 - w1) - (w2 - w3));
+                    u[i1] = 0.5f * ((w0 - w1) + (w2 - w3));
+                }
             }
         __syncthreads();
     }
@@ -274,7 +318,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
             const float R = (n > 0) ? s_r[k][j] : s_i[k][j];
             float zh, zl;
             ln_ratio_df(a.iref[k], R, zh, zl);
-            df_add(zh, zl, s_u[k][j << n] * invB);
+            if constexpr (DF)
+                df_add2(zh, zl, s_u[k][j << n] * invB, s_i[k][j << n] * invB);
+            else
+                df_add(zh, zl, s_u[k][j << n] * invB);
             const size_t o = (size_t)s.br * d.wl + s.blk0 + j;
             a.z[((size_t)s.f * 6 + k) * d.LL + o] = zh;
             a.z[((size_t)s.f * 6 + 3 + k) * d.LL + o] = zl;
@@ -285,7 +332,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
             for (int k = 0; k < 3; ++k) {
                 const float R = (n > 0) ? s_r[k][j] : s_i[k][j];
                 ln_ratio_df(a.iref[k], R, zh[k], zl[k]);
-                df_add(zh[k], zl[k], s_u[k][j << n] * invB);
+                if constexpr (DF)
+                    df_add2(zh[k], zl[k], s_u[k][j << n] * invB, s_i[k][j << n] * invB);
+                else
+                    df_add(zh[k], zl[k], s_u[k][j << n] * invB);
             }
             float sh = zh[0], sl = zl[0];
             df_add2(sh, sl, zh[1], zl[1]);
@@ -312,8 +362,22 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
             float ox = 0.0f, oy = 0.0f;
             if (((r | c) & (B - 1)) != 0) {
                 const float d0 = s_u[0][r * Wt + c], d1 = s_u[1][r * Wt + c], d2 = s_u[2][r * Wt + c];
-                ox = fmaf(m0, d0, fmaf(m1, d1, m2 * d2));
-                oy = fmaf(m3, d0, fmaf(m4, d1, m5 * d2));
+                if constexpr (DF) {
+                    // every low part is read before this thread overwrites its element
+                    const float e0 = s_i[0][r * Wt + c], e1 = s_i[1][r * Wt + c], e2 = s_i[2][r * Wt + c];
+                    float xh = 0.0f, xl = 0.0f, yh = 0.0f, yl = 0.0f;
+                    df_mul_add(xh, xl, m0, a.M[8], d0, e0);
+                    df_mul_add(xh, xl, m1, a.M[9], d1, e1);
+                    df_mul_add(xh, xl, m2, a.M[10], d2, e2);
+                    df_mul_add(yh, yl, m3, a.M[11], d0, e0);
+                    df_mul_add(yh, yl, m4, a.M[12], d1, e1);
+                    df_mul_add(yh, yl, m5, a.M[13], d2, e2);
+                    ox = xh + xl;
+                    oy = yh + yl;
+                } else {
+                    ox = fmaf(m0, d0, fmaf(m1, d1, m2 * d2));
+                    oy = fmaf(m3, d0, fmaf(m4, d1, m5 * d2));
+                }
             }
             s_i[0][r * Wt + c] = ox;
             s_i[1][r * Wt + c] = oy;
@@ -1343,11 +1407,15 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W
 
 // Logit minus the reference, nm - |r - v_j|^2 (nm = -m), with r and node j's
 // coordinates v_j = C + LO held as double-floats: the differences, their
-// squares and the sum carry their rounding errors, so the result is exact to
-// a float32 rounding of itself (a float32 difference form rounds at the
-// scale of |r| and |v_j| instead, which coarse grids make large).
+// squares and the sum carry their rounding errors, and the result is
+// returned as a double-float (high part returned, low part in tl), so the
+// weight exp2(t) (1 + tl ln 2) is free of the logit's float32 rounding too
+// (a float32 difference form rounds at the scale of |r| and |v_j| instead,
+// which coarse grids make large; on grids with very few nodes even the
+// rounding of the logit itself, at a scale of tens of units, moves a
+// posterior mean between two distant nodes by up to 1e-4 uM).
 __device__ __forceinline__ float df_logit(const float rh[3], const float rl[3], const float *__restrict__ C,
-                                          const float *__restrict__ LO, int j, float nm) {
+                                          const float *__restrict__ LO, int j, float nm, float &tl) {
 #pragma clang fp contract(off)
     float sh = 0.0f, sl = 0.0f;
 #pragma unroll
@@ -1362,7 +1430,10 @@ __device__ __forceinline__ float df_logit(const float rh[3], const float rl[3], 
         sh = s;
         sl += es + qe;
     }
-    return (nm - sh) - sl;
+    float th, e;
+    two_sum(nm, -sh, th, e);
+    tl = e - sl;
+    return th;
 }
 
 // Direct kernel: one LL pixel per lane, logits in the difference form
@@ -1433,16 +1504,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
                     ++executed;
 #pragma unroll
                     for (int j = 0; j < kChunkNodes; ++j) {
-                        float t;
+                        float wt;
                         if (PRECISE) {
-                            t = df_logit(rh, rl, C, LO, j, nm);
+                            float tl;
+                            const float th = df_logit(rh, rl, C, LO, j, nm, tl);
+                            const float w = __builtin_amdgcn_exp2f(th);
+                            wt = fmaf(w, tl * 0.6931471805599453f, w);
                         } else {
                             const float d0 = r[0] - C[j], d1 = r[1] - C[16 + j], d2 = r[2] - C[32 + j];
-                            t = fmaf(-d0, d0, nm);
+                            float t = fmaf(-d0, d0, nm);
                             t = fmaf(-d1, d1, t);
                             t = fmaf(-d2, d2, t);
+                            wt = __builtin_amdgcn_exp2f(t);
                         }
-                        const float wt = __builtin_amdgcn_exp2f(t);
                         L0 += wt;
                         L1 = fmaf(wt, C[64 + j], L1);
                         L2 = fmaf(wt, C[80 + j], L2);
@@ -1473,13 +1547,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float2 lowpass_estimate(const RecomposeArgs &a, int f, long long q) {
     if (a.lowpass == HB_LOWPASS_TIKHONOV) {
+        // offset + M z with M, the offset and z as double-floats: the terms
+        // are about |M| |z| (~1e3 uM) while the estimate is tens of uM.
         const long long LL = a.d.LL;
         const float *zf = a.z + (size_t)f * 6 * LL;
-        const float z0 = zf[q] + zf[3 * LL + q], z1 = zf[LL + q] + zf[4 * LL + q];
-        const float z2 = zf[2 * LL + q] + zf[5 * LL + q];
         const float *M = a.M;
-        return make_float2(M[6] + fmaf(M[0], z0, fmaf(M[1], z1, M[2] * z2)),
-                           M[7] + fmaf(M[3], z0, fmaf(M[4], z1, M[5] * z2)));
+        float hh = M[6], hl = M[14], oh = M[7], ol = M[15];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float zh = zf[k * LL + q], zl = zf[(3 + k) * LL + q];
+            df_mul_add(hh, hl, M[k], M[8 + k], zh, zl);
+            df_mul_add(oh, ol, M[3 + k], M[11 + k], zh, zl);
+        }
+        return make_float2(hh + hl, oh + ol);
     }
     const long long LL = a.d.LL;
     const float *P = a.part + (size_t)f * a.split * kPartFields * LL + q;
@@ -1550,7 +1630,13 @@ void launch_k1(const void *frames, const HaarArgs &b, hipStream_t s) {
         else launch_reg<T, 2>(frames, b, blocks, s);
     } else {
         const long long grid = (long long)b.n_frames * b.d.hl * b.d.strips_per_row;
-        hipLaunchKernelGGL(k_log_haar<T>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, (const T *)frames, c);
+        // Up to two levels the strip kernel keeps the register kernel's bits.
+        if (n >= 3)
+            hipLaunchKernelGGL((k_log_haar<T, true>), dim3((unsigned)grid), dim3(kBlockThreads), 0, s,
+                               (const T *)frames, c);
+        else
+            hipLaunchKernelGGL((k_log_haar<T, false>), dim3((unsigned)grid), dim3(kBlockThreads), 0, s,
+                               (const T *)frames, c);
     }
 }
 

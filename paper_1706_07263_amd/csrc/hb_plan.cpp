@@ -38,7 +38,7 @@ struct hb_plan_s {
     // Device memory.
     double *d_k0 = nullptr;   // K0 inputs followed by outputs
     size_t k0_in = 0;         // doubles of K0 input
-    float *d_mf = nullptr;    // FP32 M (6) + low-pass Tikhonov offset (2)
+    float *d_mf = nullptr;    // M (6) and the low-pass Tikhonov offset (2) as float32, then their low parts
     float *d_tiles = nullptr;   // super-tile table
     float *d_lo = nullptr;      // low parts of the node coordinates (double-float direct logits)
     void *d_split = nullptr;    // split bf16 A operands of the chunks
@@ -685,7 +685,7 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     const size_t LL = (size_t)p->dims.LL;
     const size_t HW = (size_t)desc->height * desc->width;
     st = HB_OK;
-    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_mf, sizeof(float) * 8);
+    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_mf, sizeof(float) * 16);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_tiles, sizeof(float) * (size_t)p->n_tiles * super_floats(p->side));
     if (st == HB_OK)
         st = dev_alloc(p, &p->d_split, (size_t)kSplitChunkBytes * p->n_tiles * (p->side / 4) * (p->side / 4));
@@ -805,13 +805,16 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
 
     // Low-pass Tikhonov offset: c_ref + M (r - mu_ref), so that the low-pass
     // estimate is that offset + M z with z = ybar - r.
-    float mf_extra[2];
+    // Float32 value and low part of each (the device's M parts come from K0).
+    float mf_extra[2], mf_extra_lo[2];
     for (int i = 0; i < 2; ++i) {
         double v = (i == 0 ? ref_hb : ref_hbo2);
         for (int k = 0; k < 3; ++k) v += k0_out[6 + 3 * i + k] * (r[k] - mu_ref[k]);
         mf_extra[i] = (float)v;
+        mf_extra_lo[i] = (float)(v - (double)mf_extra[i]);
     }
-    if (hipMemcpy(p->d_mf + 6, mf_extra, sizeof(mf_extra), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(p->d_mf + 6, mf_extra, sizeof(mf_extra), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_mf + 14, mf_extra_lo, sizeof(mf_extra_lo), hipMemcpyHostToDevice) != hipSuccess)
         return HB_ERR_DEVICE;
 
     std::vector<float> tiles, lo;
