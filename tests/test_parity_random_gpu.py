@@ -12,7 +12,7 @@ from tests import hbtest
 
 pytestmark = pytest.mark.gpu
 
-N_CASES = 100
+N_CASES = 300
 
 
 @pytest.fixture(scope="module")
