@@ -262,7 +262,8 @@ def run_timed(hb, torch, plan, frames, maps, stream, steps, warmup, call_ms=None
     """Warm-up calls, then `steps` calls timed on the host clock between device
     synchronisations, with the plan's per-kernel HIP events and pair counter.
     Returns (seconds, stage ms per call, evaluated pairs per posterior launch,
-    full-grid pairs per launch).  With a list `call_ms`, HIP events on the
+    full-grid pairs per launch, pixels per launch whose posterior sums took
+    double-float logits for lying far from the grid's nodes).  With a list `call_ms`, HIP events on the
     launch stream around every timed call append each call's milliseconds."""
     with torch.cuda.stream(stream):
         for _ in range(warmup):
@@ -286,9 +287,11 @@ def run_timed(hb, torch, plan, frames, maps, stream, steps, warmup, call_ms=None
         call_ms.extend(e0.elapsed_time(e1) for e0, e1 in ev)
     ms, launches = hb.hb_plan_get_timing(plan.handle)
     evaluated, full = hb.hb_plan_get_work(plan.handle)
+    far = hb.hb_plan_get_far_pixels(plan.handle)
     hb.hb_plan_set_timing(plan.handle, False)
     per = ms / np.maximum(launches, 1)
-    return elapsed, per, evaluated / max(launches[1], 1), full / max(launches[1], 1)
+    n = max(launches[1], 1)
+    return elapsed, per, evaluated / n, full / n, far / n
 
 
 def time_plan(hb, torch, desc, spectra, frames, maps, stream, steps, warmup):
@@ -307,7 +310,7 @@ def posterior_modes(a, hb, torch, synth, frames, maps, stream, mix_rate):
     for name, tol, steps in (("exact_skip", 0.0, 6), ("full_grid", -1.0, 3)):
         with hb.Plan(make_desc(hb, a, W, H, B, posterior_tolerance=tol), 0) as plan:
             plan.set_forward_model(synth.spectra())
-            elapsed, per, ev, full = run_timed(hb, torch, plan, frames, maps, stream, steps, 1)
+            elapsed, per, ev, full, _ = run_timed(hb, torch, plan, frames, maps, stream, steps, 1)
         k2 = per[1] * 1e-3
         out[name] = {"posterior_tolerance_um": tol, "skip_log2": "none" if tol < 0 else 160,
                      "frames_per_s": round(steps * B / elapsed, 2), "call_ms": round(per[3], 4),
@@ -357,7 +360,7 @@ def config4_storage(a, hb, torch, synth, stream):
         fr = frames_to_device(host[dt], dt)
         with hb.Plan(make_desc(hb, a, W, H, 2, dtype=dt, levels=1, grid=512, grid_split=0), 0) as plan:
             plan.set_forward_model(synth.spectra())
-            elapsed, per, ev, full = run_timed(hb, torch, plan, fr, maps, stream, 10, 2)
+            elapsed, per, ev, full, _ = run_timed(hb, torch, plan, fr, maps, stream, 10, 2)
         out[dt] = {"frames_per_s": round(20 / elapsed, 2), "call_ms": round(per[3], 4),
                    "log_haar_ms": round(per[0], 4), "posterior_ms": round(per[1], 4),
                    "evaluated_fraction": round(ev / full, 5)}
@@ -571,8 +574,8 @@ def main():
 
     log(f"warmup {a.warmup}, timed {a.steps}", a.quiet)
     call_ms = []
-    elapsed, per, eval_per_launch, full_per_launch = run_timed(hb, torch, plan, frames, maps, stream,
-                                                               a.steps, a.warmup, call_ms)
+    elapsed, per, eval_per_launch, full_per_launch, far_per_launch = run_timed(hb, torch, plan, frames, maps,
+                                                                               stream, a.steps, a.warmup, call_ms)
     plan.close()
     log(f"timed {a.steps} steps in {elapsed:.3f} s; stage ms {per}", a.quiet)
 
@@ -601,6 +604,7 @@ def main():
         "avg_launch_ms": round(per[1], 4), "launches_timed": a.steps,
         "evaluated_pairs_per_launch": int(eval_per_launch), "full_grid_pairs_per_launch": int(full_per_launch),
         "evaluated_fraction": round(eval_per_launch / max(full_per_launch, 1), 5),
+        "far_pixels_per_launch": far_per_launch,
         "evaluated_pairs_per_s": eval_rate, "ceiling_pairs_per_s": mix_rate,
         "nominal_ceiling_pairs_per_s": NOMINAL_CEILING_PAIRS_PER_S,
         "frac_of_nominal_ceiling": round(eval_rate / NOMINAL_CEILING_PAIRS_PER_S, 4),

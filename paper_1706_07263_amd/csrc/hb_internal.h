@@ -64,6 +64,18 @@ constexpr int kSplitChunkBytes = 64 * kSplitLaneBytes;
 // and 1000 it reached 8.0e-5 uM (sigma 0.004 on a 256 x 256 grid), too
 // close to the 1e-4 uM tolerance.
 constexpr double kMfmaPrecisionBudget = 700.0;
+// The rule above holds for observations near the grid's surface in scaled
+// units (within kFarRhoMin of a node: the calibration's noisy frames).  An
+// observation at scaled distance rho from the nodes makes the expanded
+// logit's terms about (R + rho) R instead of R^2.  Measured on seeded random
+// frames, the error per unit of (R + rho) R h reached 1.6e-7 uM (a 50 x 101
+// grid at sigma 0.002, whose posterior sits on few coarse nodes: 1.04e-4 uM
+// at rho = 9.0, R = 8.5, h = 4.4 uM), so the MFMA kernel forms the sums of
+// pixels with rho > max(kFarRhoMin, kMfmaFarBudget / (R h) - R) again with
+// double-float logits (rho: the soft minimum over the nodes); at the budget
+// that constant gives 5.6e-5 uM.
+constexpr double kMfmaFarBudget = 350.0;
+constexpr double kFarRhoMin = 3.0;
 // Precision rule for the direct kernel.  Its float32 difference-form logit
 // of a node at scaled distance d from the observation carries an absolute
 // error of a few d^2 u; for a pixel between two neighbouring nodes at scaled
@@ -73,6 +85,14 @@ constexpr double kMfmaPrecisionBudget = 700.0;
 // kDirectPrecisionBudget (8e-9 x 3800 = 3e-5 uM) form the logits from
 // double-float coordinate differences instead.
 constexpr double kDirectPrecisionBudget = 3800.0;
+// Precision rule for K1.  With float32 log-ratios u = ln(R/I), their rounding
+// reaches the maps through the Tikhonov operator M: measured on seeded random
+// frames, up to 7.3e-5 uM at |M|inf = 1.13e3 uM per unit log-attenuation and
+// 1.1-1.2e-4 uM at 1.4e3-3.1e3 (two levels).  Plans whose |M|inf exceeds
+// kK1PrecisionBudget, and every plan with three or more levels, run K1 with
+// double-float log-ratios, Haar cascade and Tikhonov apply (4x the ALU work:
+// kept off the default camera, |M|inf = 1.05e3).
+constexpr double kK1PrecisionBudget = 1100.0;
 // Low parts of a chunk's node coordinates (3 coordinates x 16 nodes).
 constexpr int kLoFloats = 48;
 
@@ -155,6 +175,7 @@ struct HaarArgs {
     float *z;                // [n][6][LL]: high parts R,G,B then low parts
     float2 *det;             // [n][H][W] spatial detail part (inverse Haar of the details)
     int project;             // project z onto the plane orthogonal to (1,1,1)
+    int df;                  // double-float log-ratios, Haar and Tikhonov (always from three levels on)
 };
 
 struct PosteriorArgs {
@@ -176,7 +197,10 @@ struct PosteriorArgs {
     float *part;             // [n][split][kPartFields][LL]
     const float *lo;         // direct kernel: [chunk][kLoFloats] coordinate low parts for
                              // double-float logits, or null for float32 logits
-    unsigned long long *work;  // optional: pairs evaluated (pixel x node), added per wave
+    unsigned long long *work;  // optional: [0] pairs evaluated (pixel x node), added per wave,
+                               // [1] (pixel, split) sums formed again with double-float logits
+    float far_rho2;          // MFMA kernel: pixels whose squared soft-minimum distance to the
+                             // nodes exceeds this take double-float logits (INFINITY: none)
     // Fused recomposition (one split, MFMA kernel, levels <= 2): the kernel
     // writes the low-pass estimate and the maps itself instead of partials.
     int fuse;

@@ -472,7 +472,7 @@ __device__ __forceinline__ void store_row(float2 *p, const float2 *o) {
     }
 }
 
-template <typename T, int N>
+template <typename T, int N, bool DF>
 __global__ __launch_bounds__(kBlockThreads) void k_log_haar_reg(const T *__restrict__ frames, HaarArgs a) {
     constexpr int BW = 1 << N, NP = BW * BW;
     const Dims &d = a.d;
@@ -519,11 +519,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar_reg(const T *__restr
     }
 
     // 3. Log-ratio to the block mean; 4. Haar in place (window * H, Eq. 1-2).
+    //    DF: u, the cascade and (step 6) the Tikhonov apply as double-floats
+    //    (low parts in ul), as in the strip kernel.
+    float ul[3][NP];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const float rinv = 1.0f / R[k];
 #pragma unroll
-        for (int i = 0; i < NP; ++i) u[k][i] = neg_log_ratio(I[k][i], R[k], rinv);
+        for (int i = 0; i < NP; ++i) {
+            if constexpr (DF)
+                ln_ratio_df(R[k], I[k][i], u[k][i], ul[k][i]);   // ln(R / I) = -ln(I / R)
+            else
+                u[k][i] = neg_log_ratio(I[k][i], R[k], rinv);
+        }
 #pragma unroll
         for (int l = 1; l <= N; ++l) {
             const int h = 1 << (l - 1), g2 = 2 * h;
@@ -531,12 +539,35 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar_reg(const T *__restr
             for (int r = 0; r < BW; r += g2)
 #pragma unroll
                 for (int c = 0; c < BW; c += g2) {
-                    const float w0 = u[k][r * BW + c], w1 = u[k][r * BW + c + h];
-                    const float w2 = u[k][(r + h) * BW + c], w3 = u[k][(r + h) * BW + c + h];
-                    u[k][r * BW + c] = 0.5f * ((w0 + w1) + (w2 + w3));
-                    u[k][(r + h) * BW + c] = 0.5f * ((w0 + w1) - (w2 + w3));
-                    u[k][(r + h) * BW + c + h] = 0.5f * ((w0 - w1) - (w2 - w3));
-                    u[k][r * BW + c + h] = 0.5f * ((w0 - w1) + (w2 - w3));
+                    const int i0 = r * BW + c, i1 = i0 + h, i2 = (r + h) * BW + c, i3 = i2 + h;
+                    if constexpr (DF) {
+                        float ah = u[k][i0], al = ul[k][i0], bh = u[k][i2], bl = ul[k][i2];
+                        float ch = ah, cl = al, dh = bh, dl = bl;
+                        df_add2(ah, al, u[k][i1], ul[k][i1]);     // w0 + w1
+                        df_add2(bh, bl, u[k][i3], ul[k][i3]);     // w2 + w3
+                        df_add2(ch, cl, -u[k][i1], -ul[k][i1]);   // w0 - w1
+                        df_add2(dh, dl, -u[k][i3], -ul[k][i3]);   // w2 - w3
+                        float llh = ah, lll = al, d1h = ah, d1l = al, d2h = ch, d2l = cl, d3h = ch, d3l = cl;
+                        df_add2(llh, lll, bh, bl);
+                        df_add2(d1h, d1l, -bh, -bl);
+                        df_add2(d2h, d2l, -dh, -dl);
+                        df_add2(d3h, d3l, dh, dl);
+                        u[k][i0] = 0.5f * llh;
+                        ul[k][i0] = 0.5f * lll;
+                        u[k][i2] = 0.5f * d1h;
+                        ul[k][i2] = 0.5f * d1l;
+                        u[k][i3] = 0.5f * d2h;
+                        ul[k][i3] = 0.5f * d2l;
+                        u[k][i1] = 0.5f * d3h;
+                        ul[k][i1] = 0.5f * d3l;
+                    } else {
+                        const float w0 = u[k][i0], w1 = u[k][i1];
+                        const float w2 = u[k][i2], w3 = u[k][i3];
+                        u[k][i0] = 0.5f * ((w0 + w1) + (w2 + w3));
+                        u[k][i2] = 0.5f * ((w0 + w1) - (w2 + w3));
+                        u[k][i3] = 0.5f * ((w0 - w1) - (w2 - w3));
+                        u[k][i1] = 0.5f * ((w0 - w1) + (w2 - w3));
+                    }
                 }
         }
     }
@@ -547,7 +578,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar_reg(const T *__restr
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         ln_ratio_df(a.iref[k], R[k], zh[k], zl[k]);
-        df_add(zh[k], zl[k], u[k][0] * invB);
+        if constexpr (DF)
+            df_add2(zh[k], zl[k], u[k][0] * invB, ul[k][0] * invB);
+        else
+            df_add(zh[k], zl[k], u[k][0] * invB);
     }
     if (a.project) {
         float sh = zh[0], sl = zl[0];
@@ -573,8 +607,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar_reg(const T *__restr
         o[0][i] = o[1][i] = 0.0f;
         if (i != 0) {
             const float d0 = u[0][i], d1 = u[1][i], d2 = u[2][i];
-            o[0][i] = fmaf(m0, d0, fmaf(m1, d1, m2 * d2));
-            o[1][i] = fmaf(m3, d0, fmaf(m4, d1, m5 * d2));
+            if constexpr (DF) {
+                float xh = 0.0f, xl = 0.0f, yh = 0.0f, yl = 0.0f;
+                df_mul_add(xh, xl, m0, a.M[8], d0, ul[0][i]);
+                df_mul_add(xh, xl, m1, a.M[9], d1, ul[1][i]);
+                df_mul_add(xh, xl, m2, a.M[10], d2, ul[2][i]);
+                df_mul_add(yh, yl, m3, a.M[11], d0, ul[0][i]);
+                df_mul_add(yh, yl, m4, a.M[12], d1, ul[1][i]);
+                df_mul_add(yh, yl, m5, a.M[13], d2, ul[2][i]);
+                o[0][i] = xh + xl;
+                o[1][i] = yh + yl;
+            } else {
+                o[0][i] = fmaf(m0, d0, fmaf(m1, d1, m2 * d2));
+                o[1][i] = fmaf(m3, d0, fmaf(m4, d1, m5 * d2));
+            }
         }
     }
 #pragma unroll
@@ -730,6 +776,14 @@ __device__ __forceinline__ bf16x8 split_pixel_operand(float u, float c, bool coo
     b[2] = p23;                                                  // (x2, x3)
     b[3] = coord ? p23 : 0u;                                     // (x2, x3) or (0, 0)
     return __builtin_bit_cast(bf16x8, b);
+}
+
+// (p, pe) = r^2 exactly (product and its FMA residual) if sq, else (m, 0).
+__device__ __forceinline__ void square_or(float r, float m, bool sq, float &p, float &pe) {
+#pragma clang fp contract(off)
+    const float rr = r * r;
+    p = sq ? rr : m;
+    pe = sq ? fmaf(r, r, -rr) : 0.0f;
 }
 
 constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
@@ -1094,8 +1148,7 @@ __device__ float far_gap_max(const PosteriorArgs &a, const WaveWork &w, const fl
 template <int PB, int V>
 __device__ __forceinline__ void fused_maps(const PosteriorArgs &a, const WaveWork &w, const float *anc_hb,
                                            const float *anc_ox, const float *R0, const float *R1,
-                                           const float *R2) {
-    const int lane = threadIdx.x & 63;
+                                           const float *R2, int lane) {
     const int lp = lane & 15, lk = lane >> 4;
     const int n = a.levels, B = 1 << n;
     float ex[PB], ey[PB];
@@ -1129,6 +1182,145 @@ __device__ __forceinline__ void fused_maps(const PosteriorArgs &a, const WaveWor
         load_detail<V>(a.det, o, dp);
         write_maps<V>(a.hb, a.hbo2, a.thb, a.so2, a.thb_eps, o, e, dp);
     }
+}
+
+// Logit minus the reference, nm - |r - v_j|^2 (nm = -m), with r and node j's
+// coordinates v_j = C + LO held as double-floats: the differences, their
+// squares and the sum carry their rounding errors, and the result is
+// returned as a double-float (high part returned, low part in tl), so the
+// weight exp2(t) (1 + tl ln 2) is free of the logit's float32 rounding too
+// (a float32 difference form rounds at the scale of |r| and |v_j| instead,
+// which coarse grids make large; on grids with very few nodes even the
+// rounding of the logit itself, at a scale of tens of units, moves a
+// posterior mean between two distant nodes by up to 1e-4 uM).
+__device__ __forceinline__ float df_logit_v(const float rh[3], const float rl[3], const float vh[3],
+                                            const float vl[3], float nm, float &tl) {
+#pragma clang fp contract(off)
+    float sh = 0.0f, sl = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float dh, e;
+        two_sum(rh[k], -vh[k], dh, e);
+        const float dl = e + (rl[k] - vl[k]);
+        const float q = dh * dh;
+        const float qe = fmaf(2.0f * dh, dl, fmaf(dh, dh, -q));
+        float s, es;
+        two_sum(sh, q, s, es);
+        sh = s;
+        sl += es + qe;
+    }
+    float th, e;
+    two_sum(nm, -sh, th, e);
+    tl = e - sl;
+    return th;
+}
+
+__device__ __forceinline__ float df_logit(const float rh[3], const float rl[3], const float *__restrict__ C,
+                                          const float *__restrict__ LO, int j, float nm, float &tl) {
+    const float vh[3] = {C[j], C[16 + j], C[32 + j]}, vl[3] = {LO[j], LO[16 + j], LO[32 + j]};
+    return df_logit_v(rh, rl, vh, vl, nm, tl);
+}
+
+// The same pointer, hidden from the optimiser: loads through it are issued
+// where they are written instead of being merged with earlier ones.
+template <typename P>
+__device__ __forceinline__ P *opaque(P *p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// The kernel's argument as it lies in the argument segment (address space 4).
+using KernArgs = const __attribute__((address_space(4))) PosteriorArgs;
+
+// The fields the far-pixel pass reads, loaded from the argument segment.
+__device__ __forceinline__ PosteriorArgs far_args(KernArgs *k) {
+    PosteriorArgs f{};
+    f.LL = k->LL;
+    f.hl = k->hl;
+    f.wl = k->wl;
+    f.z = k->z;
+    f.scale = k->scale;
+    f.gref = k->gref;
+    f.far_rho2 = k->far_rho2;
+    f.skip_log2 = k->skip_log2;
+    f.supers = k->supers;
+    f.super_stride = k->super_stride;
+    f.chunks_per_super = k->chunks_per_super;
+    f.lo = k->lo;
+    return f;
+}
+
+// A lane value the optimiser cannot trace back (it is formed again where used).
+__device__ __forceinline__ int opaque_v(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Posterior sums of one pixel over the wave's split with double-float logits
+// (as the precise direct kernel forms them), for observations too far from the
+// grid's surface for the MFMA kernel's expanded logit.  The whole wave works
+// on the pixel: super-tiles one after another, lane l on node l % 16 of
+// chunks l / 16, l / 16 + 4, ...  Skipping is the hard rule against the
+// pixel's own reference m_skip (no budget band); nm = -m is the logit
+// reference of the sums.  Returns the sums S0, S1, S2 about the anchors on
+// every lane.
+__device__ __forceinline__ void far_pixel_sums(const PosteriorArgs &a, const WaveWork &w, const float qh[3],
+                                               const float ql[3], float m_skip, float nm, float anc_hb,
+                                               float anc_ox, float S[3]) {
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 15;
+    const float nskip = -a.skip_log2;
+    float zbox[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        zbox[k] = (qh[k] + ql[k]) - kBoxSlack;
+        zbox[3 + k] = (qh[k] + ql[k]) + kBoxSlack;
+    }
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    for (int si = w.s0; si < w.s1; ++si) {
+        float rbox[6];
+        if (!(wave_super_bound(a, si, zbox, zbox + 3, rbox) - m_skip > nskip)) continue;
+        const float *__restrict__ T = a.supers + (size_t)si * a.super_stride;
+        float rh[3], rl[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float sk, e;
+            two_sum(qh[k], -T[k], sk, e);
+            fast_two_sum(sk, e + (ql[k] - T[3 + k]), rh[k], rl[k]);
+        }
+        const float *__restrict__ C0 = T + kSupHdr + kMaxProbes * kProbeFloats;
+        const float *__restrict__ LO0 = a.lo + (size_t)si * a.chunks_per_super * kLoFloats;
+        float L0 = 0.f, L1 = 0.f, L2 = 0.f;
+        for (int ci = lane >> 4; ci < a.chunks_per_super; ci += 4) {
+            const float *__restrict__ C = C0 + (size_t)ci * kChunkFloats;
+            if (box_box_bound(C + 96, zbox) - m_skip > nskip) {
+                float tl;
+                const float th = df_logit(rh, rl, C, LO0 + (size_t)ci * kLoFloats, j, nm, tl);
+                const float e = __builtin_amdgcn_exp2f(th);
+                const float wt = fmaf(e, tl * 0.6931471805599453f, e);
+                L0 += wt;
+                L1 = fmaf(wt, C[64 + j], L1);
+                L2 = fmaf(wt, C[80 + j], L2);
+            }
+        }
+        kahan_add(s0, c0, L0);
+        kahan_add(s1, c1, fmaf(T[6] - anc_hb, L0, L1));
+        kahan_add(s2, c2, fmaf(T[7] - anc_ox, L0, L2));
+    }
+    // Sum over the 64 lanes, each pairwise step carrying its rounding error.
+    float x[3] = {s0 - c0, s1 - c1, s2 - c2}, e[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int o = 1; o <= 32; o <<= 1)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float y = __shfl_xor(x[k], o), ye = __shfl_xor(e[k], o);
+            float t, err;
+            two_sum(x[k], y, t, err);
+            x[k] = t;
+            e[k] = (e[k] + ye) + err;
+        }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) S[k] = x[k] + e[k];
 }
 
 // MFMA kernel: a wave takes PB blocks of 16 LL pixels.  Per super-tile,
@@ -1268,11 +1460,21 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
             const float r = (ah[b] - ch) + (al[b] - cl);
-            // |r|^2 + m over the pixel's four lanes (same value on each)
-            float a2 = lk < 3 ? r * r : am[b];
-            a2 += __shfl_xor(a2, 16);
-            a2 += __shfl_xor(a2, 32);
-            av[b] = split_pixel_operand(2.0f * r, -a2, lk < 3);
+            // |r|^2 + m over the pixel's four lanes (same value on each), as a
+            // double-float: observations far from the grid's nodes (small
+            // sigma, noisy frames) make both terms much larger than their
+            // sum, which float32 would round at the scale of |r|^2
+            float p, pe;
+            square_or(r, am[b], lk < 3, p, pe);
+#pragma unroll
+            for (int o = 16; o <= 32; o <<= 1) {
+                const float q = __shfl_xor(p, o), qe = __shfl_xor(pe, o);
+                float s, e;
+                two_sum(p, q, s, e);
+                p = s;
+                pe = (pe + qe) + e;
+            }
+            av[b] = split_pixel_operand(2.0f * r, -(p + pe), lk < 3);
         }
         float L0[PB], L1[PB], L2[PB];
         const int s_first = si * a.chunks_per_super;   // first chunk of the super-tile in the split table
@@ -1369,8 +1571,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W
       }
     }
 
-    if (a.work && lane == 0) atomicAdd(a.work, (unsigned long long)executed * PW * kChunkNodes);
-
     // Reduce over the four chunk-row lanes of each pixel with compensated
     // (two-sum) pairwise steps, then lanes with lk == 0 write.
 #pragma unroll
@@ -1379,22 +1579,90 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W
         R1[b] = lane_sum_rows(R1[b]);
         R2[b] = lane_sum_rows(R2[b]);
     }
+
+    // Pixels whose observation lies farther than sqrt(far_rho2) (scaled
+    // units) from the grid's nodes: the expanded logit's terms grow with that
+    // distance, so their sums are formed again with double-float logits (the
+    // plan sets far_rho2 from the precision budget).  The distance is the
+    // soft minimum over the split's nodes, rho^2 = -log2 sum_j 2^-|r - v_j|^2
+    // = -(m + log2 S0), at most the nearest node's; with a split grid, also
+    // that of the best probe of the whole grid (-gref): a split whose nodes
+    // all lie far from an observation that lies close to others carries a
+    // negligible part of the posterior.
+    unsigned far_pixels = 0;
+    static_assert(PW <= 64, "one mask bit per pixel of the wave");
+    unsigned long long far = 0;
+    // Lane indices for what follows, formed here again rather than kept
+    // across the main loop.
+    const int lane_e = opaque_v((int)threadIdx.x) & 63;
+    const int lp_e = lane_e & 15, lk_e = lane_e >> 4;
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+        long long p;
+        const bool valid = wave_pixel(a, w, b * 16 + lp_e, p);
+        const float m = __shfl(ref.m, b * 16 + lp_e);
+        far |= (__ballot(lk_e == 0 && valid && m + __log2f(R0[b]) < -a.far_rho2) & 0xffffull) << (16 * b);
+    }
+    // The pass reads the kernel's arguments again from the argument segment
+    // (PosteriorArgs is the kernel's only argument): keeping the values it
+    // needs live across the main loop would cost that loop registers.
+    KernArgs *ka = (KernArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    while (__builtin_expect(far != 0, 0)) {
+        const PosteriorArgs fa = far_args(opaque(ka));
+        const int q = __builtin_ctzll(far);   // pixel q of the wave: block q / 16, row lane q % 16
+        far &= far - 1;
+        const int qb = q >> 4, ql16 = q & 15;
+        float xa = anc_hb[0], xo = anc_ox[0];
+#pragma unroll
+        for (int b = 1; b < PB; ++b)
+            if (qb == b) {
+                xa = anc_hb[b];
+                xo = anc_ox[b];
+            }
+        long long pq;
+        wave_pixel(fa, w, q, pq);
+        const float *zq = fa.z + (size_t)w.f * 6 * fa.LL;
+        float qh[3], qlo[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) load_obs(zq, fa.LL, pq, k, fa.scale, qh[k], qlo[k]);
+        const float mq = __shfl(ref.m, q);
+        float m_skip = mq;
+        if (fa.gref) {
+            const float g = fa.gref[(size_t)w.f * fa.LL + pq];
+            if (!(g < -fa.far_rho2)) continue;
+            m_skip = fmaxf(m_skip, g);
+        }
+        ++far_pixels;
+        float S[3];
+        far_pixel_sums(fa, w, qh, qlo, m_skip, -mq, __shfl(xa, ql16), __shfl(xo, ql16), S);
+#pragma unroll
+        for (int b = 0; b < PB; ++b)
+            if (qb == b && lp_e == ql16) {
+                R0[b] = S[0];
+                R1[b] = S[1];
+                R2[b] = S[2];
+            }
+    }
+    if (a.work && lane == 0) {
+        atomicAdd(a.work, (unsigned long long)executed * PW * kChunkNodes);
+        if (far_pixels) atomicAdd(a.work + 1, (unsigned long long)far_pixels);
+    }
     if (a.fuse) {
         switch (a.vec) {
-            case 4: fused_maps<PB, 4>(a, w, anc_hb, anc_ox, R0, R1, R2); break;
-            case 2: fused_maps<PB, 2>(a, w, anc_hb, anc_ox, R0, R1, R2); break;
-            default: fused_maps<PB, 1>(a, w, anc_hb, anc_ox, R0, R1, R2); break;
+            case 4: fused_maps<PB, 4>(a, w, anc_hb, anc_ox, R0, R1, R2, lane_e); break;
+            case 2: fused_maps<PB, 2>(a, w, anc_hb, anc_ox, R0, R1, R2, lane_e); break;
+            default: fused_maps<PB, 1>(a, w, anc_hb, anc_ox, R0, R1, R2, lane_e); break;
         }
         return;
     }
     float *out = a.part + ((size_t)w.f * a.split + w.split) * kPartFields * a.LL;
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
-        const int src = b * 16 + lp;
+        const int src = b * 16 + lp_e;
         const float m = __shfl(ref.m, src);
         long long p;
         const bool valid = wave_pixel(a, w, src, p);
-        if (lk == 0 && valid) {
+        if (lk_e == 0 && valid) {
             out[p] = m;
             out[a.LL + p] = R0[b];
             out[2 * a.LL + p] = R1[b];
@@ -1405,36 +1673,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W
     }
 }
 
-// Logit minus the reference, nm - |r - v_j|^2 (nm = -m), with r and node j's
-// coordinates v_j = C + LO held as double-floats: the differences, their
-// squares and the sum carry their rounding errors, and the result is
-// returned as a double-float (high part returned, low part in tl), so the
-// weight exp2(t) (1 + tl ln 2) is free of the logit's float32 rounding too
-// (a float32 difference form rounds at the scale of |r| and |v_j| instead,
-// which coarse grids make large; on grids with very few nodes even the
-// rounding of the logit itself, at a scale of tens of units, moves a
-// posterior mean between two distant nodes by up to 1e-4 uM).
-__device__ __forceinline__ float df_logit(const float rh[3], const float rl[3], const float *__restrict__ C,
-                                          const float *__restrict__ LO, int j, float nm, float &tl) {
-#pragma clang fp contract(off)
-    float sh = 0.0f, sl = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        float dh, e;
-        two_sum(rh[k], -C[16 * k + j], dh, e);
-        const float dl = e + (rl[k] - LO[16 * k + j]);
-        const float q = dh * dh;
-        const float qe = fmaf(2.0f * dh, dl, fmaf(dh, dh, -q));
-        float s, es;
-        two_sum(sh, q, s, es);
-        sh = s;
-        sl += es + qe;
-    }
-    float th, e;
-    two_sum(nm, -sh, th, e);
-    tl = e - sl;
-    return th;
-}
 
 // Direct kernel: one LL pixel per lane, logits in the difference form
 // t - m = -(r - v_g)^2 - m on the VALU with wave-uniform (scalar) node loads;
@@ -1613,8 +1851,12 @@ namespace {
 
 template <typename T, int N>
 void launch_reg(const void *frames, const HaarArgs &b, long long blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_log_haar_reg<T, N>), dim3((unsigned)blocks), dim3(kBlockThreads), 0, s,
-                       (const T *)frames, b);
+    if (b.df)
+        hipLaunchKernelGGL((k_log_haar_reg<T, N, true>), dim3((unsigned)blocks), dim3(kBlockThreads), 0, s,
+                           (const T *)frames, b);
+    else
+        hipLaunchKernelGGL((k_log_haar_reg<T, N, false>), dim3((unsigned)blocks), dim3(kBlockThreads), 0, s,
+                           (const T *)frames, b);
 }
 
 template <typename T>
@@ -1631,7 +1873,7 @@ void launch_k1(const void *frames, const HaarArgs &b, hipStream_t s) {
     } else {
         const long long grid = (long long)b.n_frames * b.d.hl * b.d.strips_per_row;
         // Up to two levels the strip kernel keeps the register kernel's bits.
-        if (n >= 3)
+        if (n >= 3 || b.df)
             hipLaunchKernelGGL((k_log_haar<T, true>), dim3((unsigned)grid), dim3(kBlockThreads), 0, s,
                                (const T *)frames, c);
         else

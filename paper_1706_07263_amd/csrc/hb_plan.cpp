@@ -28,9 +28,12 @@ struct hb_plan_s {
     Dims dims{};
     int split = 1;
     int side = 8;
+    float far_rho2 = INFINITY;  // MFMA kernel: squared room for far observations (scaled units)
     double radius = 0;        // largest super-tile radius, scaled units
+    double node_h = 0;        // node spacing, uM of Hb/HbO2 (the larger of the two grid directions)
     bool use_mfma = true;
     bool precise = false;       // direct kernel with double-float logits
+    int k1_df = 0;              // K1 in double-float (large |M|)
     int n_tiles = 0;      // super-tiles
     long long n_nodes = 0;
     bool has_model = false;
@@ -527,6 +530,7 @@ hb_status_t estimate(hb_plan_s *p, const void *d_frames, int32_t n_frames, const
     ha.z = cb.z;
     ha.det = cb.det;
     ha.project = p->desc.illumination && p->desc.lowpass == HB_LOWPASS_BAYES;
+    ha.df = p->k1_df;
 
     if (mark(0) != hipSuccess) return HB_ERR_DEVICE;
     if (launch_log_haar(d_frames, n_frames, ha, s) != hipSuccess) return HB_ERR_DEVICE;
@@ -550,7 +554,8 @@ hb_status_t estimate(hb_plan_s *p, const void *d_frames, int32_t n_frames, const
         pa.band_log2 = p->band_log2;
         pa.band_chunks = p->band_chunks;
         pa.part = cb.part;
-        pa.lo = p->precise ? p->d_lo : nullptr;
+        pa.lo = p->precise || p->use_mfma ? p->d_lo : nullptr;
+        pa.far_rho2 = p->far_rho2;
         pa.work = ev ? p->d_work : nullptr;
         if (ev) p->full_pairs += (long long)n_frames * p->dims.LL * p->n_nodes;
         if (cb.gref) {
@@ -698,8 +703,8 @@ hb_status_t hb_plan_create(const hb_plan_desc_t *desc, int device, hb_plan_t *ou
     if (st == HB_OK && desc->lowpass == HB_LOWPASS_BAYES && p->split > 1)
         st = dev_alloc(p, (void **)&p->d_gref, sizeof(float) * nb * LL);
     if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_est, sizeof(float2) * nb * LL);
-    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_work, sizeof(unsigned long long));
-    if (st == HB_OK && hipMemset(p->d_work, 0, sizeof(unsigned long long)) != hipSuccess) st = HB_ERR_DEVICE;
+    if (st == HB_OK) st = dev_alloc(p, (void **)&p->d_work, 2 * sizeof(unsigned long long));
+    if (st == HB_OK && hipMemset(p->d_work, 0, 2 * sizeof(unsigned long long)) != hipSuccess) st = HB_ERR_DEVICE;
     if (st == HB_OK && hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) {
         p->done = nullptr;
         st = HB_ERR_DEVICE;
@@ -822,8 +827,15 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
     p->radius = build_supers(d, model, r, (double)p->scale, p->side, tiles, lo, direct_index);
     const double h_thb = d.grid_thb > 1 ? (d.thb_max - d.thb_min) / (d.grid_thb - 1) : 0.0;
     const double h_so2 = d.grid_so2 > 1 ? d.thb_max * (d.so2_max - d.so2_min) / (d.grid_so2 - 1) : 0.0;
-    p->info.mfma_index = p->radius * p->radius * std::max(h_thb, h_so2);
+    p->node_h = std::max(h_thb, h_so2);
+    p->info.mfma_index = p->radius * p->radius * p->node_h;
+    // Distance from the nodes beyond which the MFMA kernel's sums take
+    // double-float logits.
+    const double rh = p->radius * p->node_h;
+    p->info.mfma_far_room = rh > 0.0 ? std::max(kFarRhoMin, kMfmaFarBudget / rh - p->radius) : INFINITY;
     p->use_mfma = p->info.mfma_index <= kMfmaPrecisionBudget;
+    p->far_rho2 = p->use_mfma && std::isfinite(p->info.mfma_far_room)
+                      ? (float)(p->info.mfma_far_room * p->info.mfma_far_room) : INFINITY;
     p->info.direct_index = direct_index;
     p->precise = !p->use_mfma && direct_index > kDirectPrecisionBudget;
     p->info.posterior_kernel = p->use_mfma ? 0 : (p->precise ? 2 : 1);
@@ -842,6 +854,13 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
         p->info.E[i] = k0_out[i];
         p->info.M[i] = k0_out[6 + i];
     }
+    double m_norm = 0.0;
+    for (int i = 0; i < 2; ++i)
+        m_norm = std::max(m_norm, std::fabs(k0_out[6 + 3 * i]) + std::fabs(k0_out[7 + 3 * i]) +
+                                      std::fabs(k0_out[8 + 3 * i]));
+    p->info.m_norm = m_norm;
+    p->k1_df = (m_norm > kK1PrecisionBudget || p->dims.levels >= 3) ? 1 : 0;
+    p->info.k1_double_float = p->k1_df;
     p->info.gamma = k0_out[12];
     p->info.ref_hb = ref_hb;
     p->info.ref_hbo2 = ref_hbo2;
@@ -890,7 +909,7 @@ hb_status_t hb_plan_set_timing(hb_plan_t p, int32_t enable) {
     if (!p) return HB_ERR_INVALID_ARG;
     if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return HB_ERR_DEVICE;
-    if (hipMemset(p->d_work, 0, sizeof(unsigned long long)) != hipSuccess) return HB_ERR_DEVICE;
+    if (hipMemset(p->d_work, 0, 2 * sizeof(unsigned long long)) != hipSuccess) return HB_ERR_DEVICE;
     p->full_pairs = 0;
     p->timing = enable != 0;
     p->timed_calls = 0;
@@ -905,6 +924,16 @@ hb_status_t hb_plan_get_work(hb_plan_t p, int64_t *evaluated, int64_t *full) {
     if (hipMemcpy(&v, p->d_work, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return HB_ERR_DEVICE;
     *evaluated = (int64_t)v;
     *full = p->full_pairs;
+    return HB_OK;
+}
+
+hb_status_t hb_plan_get_far_pixels(hb_plan_t p, int64_t *pixels) {
+    if (!p || !pixels) return HB_ERR_INVALID_ARG;
+    if (set_device(p->device) != HB_OK) return HB_ERR_DEVICE;
+    unsigned long long v = 0;
+    if (hipDeviceSynchronize() != hipSuccess) return HB_ERR_DEVICE;
+    if (hipMemcpy(&v, p->d_work + 1, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return HB_ERR_DEVICE;
+    *pixels = (int64_t)v;
     return HB_OK;
 }
 

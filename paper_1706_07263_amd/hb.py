@@ -80,7 +80,9 @@ class hb_plan_info_t(ctypes.Structure):
                 ("n_tiles", ctypes.c_int32), ("posterior_kernel", ctypes.c_int32),
                 ("n_nodes", ctypes.c_int64), ("skip_log2", ctypes.c_double), ("skip_bound", ctypes.c_double),
                 ("mfma_index", ctypes.c_double), ("direct_index", ctypes.c_double),
-                ("band_log2", ctypes.c_double), ("band_chunks", ctypes.c_int64)]
+                ("band_log2", ctypes.c_double), ("band_chunks", ctypes.c_int64),
+                ("mfma_far_room", ctypes.c_double), ("m_norm", ctypes.c_double),
+                ("k1_double_float", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -101,14 +103,16 @@ _lib.hb_plan_set_timing.argtypes = [_P, ctypes.c_int32]
 _lib.hb_plan_get_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 _lib.hb_debug_copy.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]
 _lib.hb_plan_get_work.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+_lib.hb_plan_get_far_pixels.argtypes = [_P, ctypes.POINTER(ctypes.c_int64)]
 for _f in ("hb_plan_desc_default", "hb_plan_create", "hb_set_forward_model", "hb_estimate_frames",
            "hb_estimate_frames_noalloc", "hb_destroy", "hb_plan_get_info", "hb_plan_set_timing", "hb_plan_get_timing", "hb_debug_copy",
-           "hb_plan_get_work"):
+           "hb_plan_get_work", "hb_plan_get_far_pixels"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("hb_plan_desc_default", "hb_plan_create", "hb_set_forward_model", "hb_estimate_frames",
             "hb_estimate_frames_noalloc", "hb_destroy", "hb_status_string", "hb_plan_device_bytes", "hb_plan_get_info",
-            "hb_plan_set_timing", "hb_plan_get_timing", "hb_debug_copy", "hb_plan_get_work")
+            "hb_plan_set_timing", "hb_plan_get_timing", "hb_debug_copy", "hb_plan_get_work",
+            "hb_plan_get_far_pixels")
 
 
 class HbError(RuntimeError):
@@ -184,7 +188,9 @@ def hb_plan_get_info(plan: int) -> Dict[str, object]:
                 grid_split=info.grid_split, n_tiles=info.n_tiles, n_nodes=info.n_nodes,
                 posterior_kernel=("mfma", "direct", "direct_precise")[info.posterior_kernel],
                 skip_log2=info.skip_log2, skip_bound=info.skip_bound, mfma_index=info.mfma_index,
-                direct_index=info.direct_index, band_log2=info.band_log2, band_chunks=info.band_chunks)
+                direct_index=info.direct_index, band_log2=info.band_log2, band_chunks=info.band_chunks,
+                mfma_far_room=info.mfma_far_room, m_norm=info.m_norm,
+                k1_double_float=bool(info.k1_double_float))
 
 
 def hb_plan_set_timing(plan: int, enable: bool) -> None:
@@ -203,6 +209,12 @@ def hb_plan_get_work(plan: int) -> Tuple[int, int]:
     full = ctypes.c_int64()
     _check(_lib.hb_plan_get_work(_P(plan), ctypes.byref(ev), ctypes.byref(full)), "hb_plan_get_work")
     return ev.value, full.value
+
+
+def hb_plan_get_far_pixels(plan: int) -> int:
+    n = ctypes.c_int64()
+    _check(_lib.hb_plan_get_far_pixels(_P(plan), ctypes.byref(n)), "hb_plan_get_far_pixels")
+    return n.value
 
 
 def hb_debug_copy(plan: int, which: int, frame: int, out: np.ndarray) -> np.ndarray:

@@ -53,7 +53,7 @@ int main(void) {
   F(hb_plan_desc_t, thb_min) F(hb_plan_desc_t, lambda) F(hb_plan_desc_t, ref_thb)
   F(hb_plan_desc_t, lowpass) F(hb_plan_desc_t, grid_split) F(hb_plan_desc_t, illumination) F(hb_plan_desc_t, posterior_tolerance)
   F(hb_forward_model_t, eps_hb) F(hb_forward_model_t, path_length_cm)
-  F(hb_plan_info_t, gamma) F(hb_plan_info_t, grid_split) F(hb_plan_info_t, posterior_kernel) F(hb_plan_info_t, n_nodes) F(hb_plan_info_t, skip_log2) F(hb_plan_info_t, skip_bound) F(hb_plan_info_t, mfma_index) F(hb_plan_info_t, direct_index) F(hb_plan_info_t, band_log2) F(hb_plan_info_t, band_chunks)
+  F(hb_plan_info_t, gamma) F(hb_plan_info_t, grid_split) F(hb_plan_info_t, posterior_kernel) F(hb_plan_info_t, n_nodes) F(hb_plan_info_t, skip_log2) F(hb_plan_info_t, skip_bound) F(hb_plan_info_t, mfma_index) F(hb_plan_info_t, direct_index) F(hb_plan_info_t, band_log2) F(hb_plan_info_t, band_chunks) F(hb_plan_info_t, mfma_far_room) F(hb_plan_info_t, m_norm) F(hb_plan_info_t, k1_double_float)
   return 0;
 }
 """)
@@ -136,6 +136,7 @@ def test_null_arguments(hb):
     assert lib.hb_plan_get_info(None, None) == hb.HB_ERR_INVALID_ARG
     assert lib.hb_debug_copy(None, 0, 0, None, 0) == hb.HB_ERR_INVALID_ARG
     assert lib.hb_plan_get_work(None, None, None) == hb.HB_ERR_INVALID_ARG
+    assert lib.hb_plan_get_far_pixels(None, None) == hb.HB_ERR_INVALID_ARG
 
 
 def test_library_has_no_cpu_fallback_symbols(hb):
