@@ -150,6 +150,8 @@ typedef struct {
                              grow as (R + distance) R, exceeds its precision budget; the MFMA kernel
                              forms the sums of pixels lying farther than this (soft minimum over the
                              nodes) again with double-float logits (hb_plan_get_far_pixels)           */
+    int32_t mfma_df_constant; /* 1: the MFMA kernel sums its pixel operand's constant |r|^2 + m as a
+                             double-float (mfma_index > 350)                                           */
     double m_norm;        /* |M|inf, uM per unit log-attenuation                                         */
     int32_t k1_double_float; /* 1: the log + Haar kernel forms log-ratios, Haar coefficients and the
                              Tikhonov apply as double-floats (|M|inf > 1100 or three or more levels:

@@ -76,6 +76,13 @@ constexpr double kMfmaPrecisionBudget = 700.0;
 // that constant gives 5.6e-5 uM.
 constexpr double kMfmaFarBudget = 350.0;
 constexpr double kFarRhoMin = 3.0;
+// Plans with R^2 h above kMfmaDfcIndex also sum the pixel operand's constant
+// |r|^2 + m as a double-float (about 0.5 more vector instructions per
+// chunk-block).  Measured on seeded random frames at sigma 0.002 on grids
+// whose nodes lie about 4 scaled units apart (the posterior on very few
+// nodes): 9.7e-5 uM with the float32 constant at R^2 h = 608, 8.6e-5 with
+// the double-float one.
+constexpr double kMfmaDfcIndex = 350.0;
 // Precision rule for the direct kernel.  Its float32 difference-form logit
 // of a node at scaled distance d from the observation carries an absolute
 // error of a few d^2 u; for a pixel between two neighbouring nodes at scaled
@@ -201,6 +208,8 @@ struct PosteriorArgs {
                                // [1] (pixel, split) sums formed again with double-float logits
     float far_rho2;          // MFMA kernel: pixels whose squared soft-minimum distance to the
                              // nodes exceeds this take double-float logits (INFINITY: none)
+    int dfc;                 // MFMA kernel: form the pixel operand's constant |r|^2 + m as a
+                             // double-float (plans with R^2 h > kMfmaDfcIndex)
     // Fused recomposition (one split, MFMA kernel, levels <= 2): the kernel
     // writes the low-pass estimate and the maps itself instead of partials.
     int fuse;

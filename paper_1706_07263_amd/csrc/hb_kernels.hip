@@ -778,13 +778,6 @@ __device__ __forceinline__ bf16x8 split_pixel_operand(float u, float c, bool coo
     return __builtin_bit_cast(bf16x8, b);
 }
 
-// (p, pe) = r^2 exactly (product and its FMA residual) if sq, else (m, 0).
-__device__ __forceinline__ void square_or(float r, float m, bool sq, float &p, float &pe) {
-#pragma clang fp contract(off)
-    const float rr = r * r;
-    p = sq ? rr : m;
-    pe = sq ? fmaf(r, r, -rr) : 0.0f;
-}
 
 constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
 // Workgroups of four waves resident at once: 256 CUs x 4 SIMDs x 6 waves / 4.
@@ -800,6 +793,14 @@ struct WaveWork {
     int f, split, s0, s1;
     int r0, c0;  // wave tile origin in LL pixels
 };
+
+// (p, pe) = r^2 exactly (product and its FMA residual) if sq, else (m, 0).
+__device__ __forceinline__ void square_or(float r, float m, bool sq, float &p, float &pe) {
+#pragma clang fp contract(off)
+    const float rr = r * r;
+    p = sq ? rr : m;
+    pe = sq ? fmaf(r, r, -rr) : 0.0f;
+}
 
 template <int PW>
 __device__ __forceinline__ WaveWork wave_work(const PosteriorArgs &a) {
@@ -1338,7 +1339,7 @@ __device__ __forceinline__ void far_pixel_sums(const PosteriorArgs &a, const Wav
 // three operand buffers, wave priority by predicted work) serves launches
 // small enough to be resident at once.  Both evaluate the same chunks in
 // the same order.
-template <int PB, int WAVES>
+template <int PB, int WAVES, bool DFC>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_posterior(PosteriorArgs a) {
     constexpr int PW = 16 * PB;
     constexpr int LPP = 64 / PW;
@@ -1460,21 +1461,26 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
             const float r = (ah[b] - ch) + (al[b] - cl);
-            // |r|^2 + m over the pixel's four lanes (same value on each), as a
-            // double-float: observations far from the grid's nodes (small
-            // sigma, noisy frames) make both terms much larger than their
-            // sum, which float32 would round at the scale of |r|^2
-            float p, pe;
-            square_or(r, am[b], lk < 3, p, pe);
+            // |r|^2 + m over the pixel's four lanes (same value on each)
+            if constexpr (DFC) {
+                // as a double-float (plans near the precision budget)
+                float p, pe;
+                square_or(r, am[b], lk < 3, p, pe);
 #pragma unroll
-            for (int o = 16; o <= 32; o <<= 1) {
-                const float q = __shfl_xor(p, o), qe = __shfl_xor(pe, o);
-                float s, e;
-                two_sum(p, q, s, e);
-                p = s;
-                pe = (pe + qe) + e;
+                for (int o = 16; o <= 32; o <<= 1) {
+                    const float q = __shfl_xor(p, o), qe = __shfl_xor(pe, o);
+                    float s, e;
+                    two_sum(p, q, s, e);
+                    p = s;
+                    pe = (pe + qe) + e;
+                }
+                av[b] = split_pixel_operand(2.0f * r, -(p + pe), lk < 3);
+            } else {
+                float a2 = lk < 3 ? r * r : am[b];
+                a2 += __shfl_xor(a2, 16);
+                a2 += __shfl_xor(a2, 32);
+                av[b] = split_pixel_operand(2.0f * r, -a2, lk < 3);
             }
-            av[b] = split_pixel_operand(2.0f * r, -(p + pe), lk < 3);
         }
         float L0[PB], L1[PB], L2[PB];
         const int s_first = si * a.chunks_per_super;   // first chunk of the super-tile in the split table
@@ -1912,10 +1918,15 @@ hipError_t launch_posterior(const PosteriorArgs &a, bool mfma, hipStream_t s) {
     // A launch whose workgroups are all resident at once runs about four
     // waves per SIMD: the variant built for four keeps more loads in flight
     // (same arithmetic, same bits).
-    if (mfma && grid <= kResidentGroups)
-        hipLaunchKernelGGL((k_posterior<kPixelBlocks, 4>), dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
+    const dim3 g((unsigned)grid), blk(kBlockThreads);
+    if (mfma && grid <= kResidentGroups && a.dfc)
+        hipLaunchKernelGGL((k_posterior<kPixelBlocks, 4, true>), g, blk, 0, s, a);
+    else if (mfma && grid <= kResidentGroups)
+        hipLaunchKernelGGL((k_posterior<kPixelBlocks, 4, false>), g, blk, 0, s, a);
+    else if (mfma && a.dfc)
+        hipLaunchKernelGGL((k_posterior<kPixelBlocks, 6, true>), g, blk, 0, s, a);
     else if (mfma)
-        hipLaunchKernelGGL((k_posterior<kPixelBlocks, 6>), dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
+        hipLaunchKernelGGL((k_posterior<kPixelBlocks, 6, false>), g, blk, 0, s, a);
     else if (a.lo)
         hipLaunchKernelGGL(k_posterior_direct<true>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
     else

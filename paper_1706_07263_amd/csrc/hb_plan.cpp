@@ -556,6 +556,7 @@ hb_status_t estimate(hb_plan_s *p, const void *d_frames, int32_t n_frames, const
         pa.part = cb.part;
         pa.lo = p->precise || p->use_mfma ? p->d_lo : nullptr;
         pa.far_rho2 = p->far_rho2;
+        pa.dfc = p->info.mfma_df_constant;
         pa.work = ev ? p->d_work : nullptr;
         if (ev) p->full_pairs += (long long)n_frames * p->dims.LL * p->n_nodes;
         if (cb.gref) {
@@ -836,6 +837,7 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
     p->use_mfma = p->info.mfma_index <= kMfmaPrecisionBudget;
     p->far_rho2 = p->use_mfma && std::isfinite(p->info.mfma_far_room)
                       ? (float)(p->info.mfma_far_room * p->info.mfma_far_room) : INFINITY;
+    p->info.mfma_df_constant = p->use_mfma && p->info.mfma_index > kMfmaDfcIndex ? 1 : 0;
     p->info.direct_index = direct_index;
     p->precise = !p->use_mfma && direct_index > kDirectPrecisionBudget;
     p->info.posterior_kernel = p->use_mfma ? 0 : (p->precise ? 2 : 1);
