@@ -253,10 +253,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
                 const float I = s_i[k][r * Wt + c];
                 const float R = (n > 0) ? s_r[k][c >> n] : I;
                 if constexpr (DF) {
-                    float uh, ul;
-                    ln_ratio_df(R, I, uh, ul);   // ln(R / I) = -ln(I / R)
+                    // with no level u = 0 exactly, and s_i keeps the intensity
+                    // that step 5 then reads as the block reference
+                    float uh = 0.0f, ul = 0.0f;
+                    if (n > 0) {
+                        ln_ratio_df(R, I, uh, ul);   // ln(R / I) = -ln(I / R)
+                        s_i[k][r * Wt + c] = ul;
+                    }
                     s_u[k][r * Wt + c] = uh;
-                    s_i[k][r * Wt + c] = ul;
                 } else {
                     s_u[k][r * Wt + c] = neg_log_ratio(I, R, 1.0f / R);
                 }
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
             float zh, zl;
             ln_ratio_df(a.iref[k], R, zh, zl);
             if constexpr (DF)
-                df_add2(zh, zl, s_u[k][j << n] * invB, s_i[k][j << n] * invB);
+                df_add2(zh, zl, s_u[k][j << n] * invB, n > 0 ? s_i[k][j << n] * invB : 0.0f);
             else
                 df_add(zh, zl, s_u[k][j << n] * invB);
             const size_t o = (size_t)s.br * d.wl + s.blk0 + j;
@@ -333,7 +337,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_log_haar(const T *__restrict_
                 const float R = (n > 0) ? s_r[k][j] : s_i[k][j];
                 ln_ratio_df(a.iref[k], R, zh[k], zl[k]);
                 if constexpr (DF)
-                    df_add2(zh[k], zl[k], s_u[k][j << n] * invB, s_i[k][j << n] * invB);
+                    df_add2(zh[k], zl[k], s_u[k][j << n] * invB, n > 0 ? s_i[k][j << n] * invB : 0.0f);
                 else
                     df_add(zh[k], zl[k], s_u[k][j << n] * invB);
             }

@@ -474,17 +474,21 @@ def test_posterior_tolerance_skips_within_its_bound(torch_cuda, tol):
 
 @pytest.mark.parametrize("levels", [0, 1, 2])
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
-def test_register_and_strip_haar_kernels_agree_bitwise(torch_cuda, levels, dtype):
+@pytest.mark.parametrize("camera", ["default", "shifted"])
+def test_register_and_strip_haar_kernels_agree_bitwise(torch_cuda, levels, dtype, camera):
     """For up to two levels the log + Haar step runs one block per thread in
     registers when the frames pointer is aligned to a block row's vector
     width; a frames pointer offset by one stored value takes the LDS strip
     kernel with scalar loads.  Both follow the same arithmetic: the maps, the
-    low-pass observation and the details agree bit for bit."""
+    low-pass observation and the details agree bit for bit.  The shifted
+    camera's Tikhonov operator (|M|inf above 1100) runs both in double-float."""
     torch = torch_cuda
-    fr, _, _ = synth.single_frame(64, 96, config=77, dtype=dtype)
+    sp = synth.spectra() if camera == "default" else synth.alt_spectra(camera)
+    fr, _, _ = synth.single_frame(64, 96, config=77, dtype=dtype, sp=sp)
     frames = fr[None]
     s = _settings(levels=levels, grid=32)
-    run = hbtest.GpuRun(96, 64, s, dtype=dtype)
+    run = hbtest.GpuRun(96, 64, s, dtype=dtype, sp=sp)
+    assert run.plan.info()["k1_double_float"] == (camera != "default")
     host = frames.view(np.int16) if dtype == "bf16" else frames
     flat = torch.from_numpy(np.ascontiguousarray(host).reshape(-1))
     aligned = flat.cuda()
@@ -500,7 +504,8 @@ def test_register_and_strip_haar_kernels_agree_bitwise(torch_cuda, levels, dtype
                      run.debug(run.hb.HB_DEBUG_LOWPASS_OBS), run.debug(run.hb.HB_DEBUG_DETAILS)))
     for x, y in zip(outs[0], outs[1]):
         assert np.array_equal(x, y, equal_nan=True)
-    hbtest.assert_maps_close(outs[0][0].transpose(1, 0, 2, 3), hbtest.run_oracle(frames, dtype, s), "register K1")
+    hbtest.assert_maps_close(outs[0][0].transpose(1, 0, 2, 3), hbtest.run_oracle(frames, dtype, s, sp=sp),
+                             f"register K1, {camera} camera")
     run.close()
 
 
