@@ -245,7 +245,9 @@ hb_status_t hb_plan_get_work(hb_plan_t plan, int64_t *evaluated, int64_t *full);
  * grid, from the best probe node of the whole grid (the expanded logit
  * would round at the scale of that distance; the posterior of step 4 is
  * unchanged, only its precision).  Their pairs are not counted by
- * hb_plan_get_work.  Synchronises the device. */
+ * hb_plan_get_work.  Synchronises the device, then writes the count to the
+ * host pointer `pixels`; HB_ERR_INVALID_ARG for a NULL plan or pointer,
+ * HB_ERR_DEVICE if the device cannot be read. */
 hb_status_t hb_plan_get_far_pixels(hb_plan_t plan, int64_t *pixels);
 
 /* Intermediate buffers of the last hb_estimate_frames call, and the plan's
