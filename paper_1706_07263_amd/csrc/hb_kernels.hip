@@ -1338,11 +1338,13 @@ __device__ __forceinline__ void far_pixel_sums(const PosteriorArgs &a, const Wav
 // loaded once for all PB blocks.  Each lane then holds 1 pixel x the 4
 // nodes of one chunk row (lane l: pixel l % 16, THb row l / 16, SO2 offsets
 // 0..3) and runs the exponentials and the moments on the VALU.
-// Two pixel blocks per wave (an 8 x 4 tile) at six waves per SIMD (80 VGPRs,
-// no spills) measured fastest on the 1080p workload; WAVES = 4 (88 VGPRs,
-// three operand buffers, wave priority by predicted work) serves launches
-// small enough to be resident at once.  Both evaluate the same chunks in
-// the same order.
+// Two pixel blocks per wave (an 8 x 4 tile) at six waves per SIMD (80 VGPRs;
+// spills only inside the far-observation pass) measured fastest on the 1080p
+// workload; WAVES = 4 (88 VGPRs, three operand buffers, wave priority by
+// predicted work) serves launches small enough to be resident at once.  Both
+// evaluate the same chunks in the same order.  DFC: the pixel operand's
+// constant |r|^2 + m summed as a double-float (plans near the precision
+// budget).
 template <int PB, int WAVES, bool DFC>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_posterior(PosteriorArgs a) {
     constexpr int PW = 16 * PB;
