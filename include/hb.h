@@ -137,7 +137,7 @@ typedef struct {
     double skip_bound;    /* uM, the stated bound on the posterior-mean change from skipping (0: exact)  */
     double mfma_index;    /* R^2 h: squared super-tile radius (scaled log-attenuation units) times the
                              node spacing (uM).  The MFMA kernel runs when it is <= 700 (for pixels
-                             far from the nodes see mfma_far_room)                                     */
+                             far from the nodes see far_room)                                          */
     double direct_index;  /* max over neighbouring grid nodes of their squared scaled distance times their
                              largest Hb/HbO2 difference (uM); float32 logits can move a posterior mean by
                              about 8e-9 times this                                                        */
@@ -145,11 +145,14 @@ typedef struct {
                              reference are skipped too, up to band_chunks of them per wave (a wave
                              covers 32 or 64 pixels); band_log2 = skip_log2: no such budget            */
     int64_t band_chunks;
-    double mfma_far_room; /* max(3, 350 / (R h) - R): how far (scaled units) an observation may lie
-                             from the grid's nodes before the MFMA kernel's expanded logit, whose terms
-                             grow as (R + distance) R, exceeds its precision budget; the MFMA kernel
-                             forms the sums of pixels lying farther than this (soft minimum over the
-                             nodes) again with double-float logits (hb_plan_get_far_pixels)           */
+    double far_room;      /* how far (scaled units) an observation may lie from the grid's nodes
+                             before the posterior kernel's float32 logits exceed its precision budget;
+                             the kernel forms the sums of pixels lying farther than this (soft minimum
+                             over the nodes) again with double-float logits (hb_plan_get_far_pixels).
+                             MFMA kernel: max(3, 350 / (R h) - R), its expanded logit's terms growing
+                             as (R + distance) R; float32 direct kernel: sqrt(1000 / h), its
+                             differences rounding at the scale of the distance; +inf for the direct
+                             kernel with double-float logits                                           */
     int32_t mfma_df_constant; /* 1: the MFMA kernel sums its pixel operand's constant |r|^2 + m as a
                              double-float (mfma_index > 350)                                           */
     double m_norm;        /* |M|inf, uM per unit log-attenuation                                         */
@@ -237,10 +240,10 @@ hb_status_t hb_plan_get_timing(hb_plan_t plan, double ms[4], int64_t launches[4]
 hb_status_t hb_plan_get_work(hb_plan_t plan, int64_t *evaluated, int64_t *full);
 
 /* Posterior sums of the calls made since the last hb_plan_set_timing
- * (counted only while timing is enabled) that the MFMA kernel formed again
+ * (counted only while timing is enabled) that the posterior kernel formed again
  * with double-float logits, one per LL pixel and grid split (grid_split in
  * hb_plan_info_t): those of pixels whose observation lies farther than the
- * plan's mfma_far_room from the split's nodes (soft minimum of the scaled
+ * plan's far_room from the split's nodes (soft minimum of the scaled
  * distances, -log2 of the sum of 2^-d^2 over the nodes) and, with a split
  * grid, from the best probe node of the whole grid (the expanded logit
  * would round at the scale of that distance; the posterior of step 4 is

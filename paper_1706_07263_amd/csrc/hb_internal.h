@@ -92,6 +92,13 @@ constexpr double kMfmaDfcIndex = 350.0;
 // kDirectPrecisionBudget (8e-9 x 3800 = 3e-5 uM) form the logits from
 // double-float coordinate differences instead.
 constexpr double kDirectPrecisionBudget = 3800.0;
+// The float32 direct kernel's differences also round at the scale of an
+// observation's distance rho from the nodes: measured on seeded random
+// frames at sigma 0.002 (noisy half-precision frames), 6e-5 to 8.3e-5 uM at
+// rho^2 h = 3600-5400 (h: node spacing in uM), i.e. up to 2e-8 uM per unit.
+// Pixels with rho^2 h > kDirectFarBudget take the double-float pass as in
+// the MFMA kernel (2e-5 uM at the budget).
+constexpr double kDirectFarBudget = 1000.0;
 // Precision rule for K1.  With float32 log-ratios u = ln(R/I), their rounding
 // reaches the maps through the Tikhonov operator M: measured on seeded random
 // frames, up to 7.3e-5 uM at |M|inf = 1.13e3 uM per unit log-attenuation and
@@ -202,12 +209,12 @@ struct PosteriorArgs {
     int band_chunks;         // budget: chunks a wave may skip between band_log2 and skip_log2
     float *gref;             // [n][LL] best probe logit over the whole grid, or null (one split)
     float *part;             // [n][split][kPartFields][LL]
-    const float *lo;         // direct kernel: [chunk][kLoFloats] coordinate low parts for
-                             // double-float logits, or null for float32 logits
+    const float *lo;         // [chunk][kLoFloats] coordinate low parts (double-float logits)
+    int precise;             // direct kernel: every logit from double-float differences
     unsigned long long *work;  // optional: [0] pairs evaluated (pixel x node), added per wave,
                                // [1] (pixel, split) sums formed again with double-float logits
-    float far_rho2;          // MFMA kernel: pixels whose squared soft-minimum distance to the
-                             // nodes exceeds this take double-float logits (INFINITY: none)
+    float far_rho2;          // pixels whose squared soft-minimum distance to the nodes exceeds
+                             // this take double-float logits (INFINITY: none)
     int dfc;                 // MFMA kernel: form the pixel operand's constant |r|^2 + m as a
                              // double-float (plans with R^2 h > kMfmaDfcIndex)
     // Fused recomposition (one split, MFMA kernel, levels <= 2): the kernel

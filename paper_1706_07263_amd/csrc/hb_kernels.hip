@@ -1689,8 +1689,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(W
 // Direct kernel: one LL pixel per lane, logits in the difference form
 // t - m = -(r - v_g)^2 - m on the VALU with wave-uniform (scalar) node loads;
 // PRECISE: from double-float differences (df_logit), for grids whose nodes
-// are too far apart for float32 logits.  Skipping, the global reference and
-// the exact maximum over kept chunks are as in the MFMA kernel.
+// are too far apart for float32 logits.  Skipping, the global reference, the
+// exact maximum over kept chunks and (float32 logits) the double-float pass
+// for far observations are as in the MFMA kernel.
 template <bool PRECISE>
 __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArgs a) {
     constexpr int PW = 64;
@@ -1779,6 +1780,42 @@ __global__ __launch_bounds__(kBlockThreads) void k_posterior_direct(PosteriorArg
         }
     }
     if (a.work && lane == 0) atomicAdd(a.work, (unsigned long long)executed * PW * kChunkNodes);
+    if constexpr (!PRECISE) {
+        // Pixels whose observation lies far from the grid's nodes: the float32
+        // differences round at the scale of that distance, so their sums are
+        // formed again with double-float logits, as in the MFMA kernel (the
+        // plan sets far_rho2 from this kernel's precision budget).
+        unsigned long long far = __ballot(valid && ref.m + __log2f(R0) < -a.far_rho2);
+        unsigned far_pixels = 0;
+        while (__builtin_expect(far != 0, 0)) {
+            const int q = __builtin_ctzll(far);   // the pixel of lane q
+            far &= far - 1;
+            float qh[3], ql[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                qh[k] = __shfl(ph[k], q);
+                ql[k] = __shfl(pl[k], q);
+            }
+            const float mq = __shfl(ref.m, q);
+            float m_skip = mq;
+            if (a.gref) {
+                long long pq;
+                wave_pixel(a, w, q, pq);
+                const float g = a.gref[(size_t)w.f * a.LL + pq];
+                if (!(g < -a.far_rho2)) continue;
+                m_skip = fmaxf(m_skip, g);
+            }
+            ++far_pixels;
+            float S[3];
+            far_pixel_sums(a, w, qh, ql, m_skip, -mq, __shfl(ref.ahb, q), __shfl(ref.aox, q), S);
+            if (lane == q) {
+                R0 = S[0];
+                R1 = S[1];
+                R2 = S[2];
+            }
+        }
+        if (a.work && lane == 0 && far_pixels) atomicAdd(a.work + 1, (unsigned long long)far_pixels);
+    }
     if (valid) {
         float *out = a.part + ((size_t)w.f * a.split + w.split) * kPartFields * a.LL;
         out[p] = ref.m;
@@ -1933,7 +1970,7 @@ hipError_t launch_posterior(const PosteriorArgs &a, bool mfma, hipStream_t s) {
         hipLaunchKernelGGL((k_posterior<kPixelBlocks, 6, true>), g, blk, 0, s, a);
     else if (mfma)
         hipLaunchKernelGGL((k_posterior<kPixelBlocks, 6, false>), g, blk, 0, s, a);
-    else if (a.lo)
+    else if (a.precise)
         hipLaunchKernelGGL(k_posterior_direct<true>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);
     else
         hipLaunchKernelGGL(k_posterior_direct<false>, dim3((unsigned)grid), dim3(kBlockThreads), 0, s, a);

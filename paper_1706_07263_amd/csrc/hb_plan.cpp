@@ -554,7 +554,8 @@ hb_status_t estimate(hb_plan_s *p, const void *d_frames, int32_t n_frames, const
         pa.band_log2 = p->band_log2;
         pa.band_chunks = p->band_chunks;
         pa.part = cb.part;
-        pa.lo = p->precise || p->use_mfma ? p->d_lo : nullptr;
+        pa.lo = p->d_lo;
+        pa.precise = p->precise ? 1 : 0;
         pa.far_rho2 = p->far_rho2;
         pa.dfc = p->info.mfma_df_constant;
         pa.work = ev ? p->d_work : nullptr;
@@ -830,16 +831,21 @@ hb_status_t hb_set_forward_model(hb_plan_t p, const hb_forward_model_t *fm) {
     const double h_so2 = d.grid_so2 > 1 ? d.thb_max * (d.so2_max - d.so2_min) / (d.grid_so2 - 1) : 0.0;
     p->node_h = std::max(h_thb, h_so2);
     p->info.mfma_index = p->radius * p->radius * p->node_h;
-    // Distance from the nodes beyond which the MFMA kernel's sums take
-    // double-float logits.
-    const double rh = p->radius * p->node_h;
-    p->info.mfma_far_room = rh > 0.0 ? std::max(kFarRhoMin, kMfmaFarBudget / rh - p->radius) : INFINITY;
     p->use_mfma = p->info.mfma_index <= kMfmaPrecisionBudget;
-    p->far_rho2 = p->use_mfma && std::isfinite(p->info.mfma_far_room)
-                      ? (float)(p->info.mfma_far_room * p->info.mfma_far_room) : INFINITY;
     p->info.mfma_df_constant = p->use_mfma && p->info.mfma_index > kMfmaDfcIndex ? 1 : 0;
     p->info.direct_index = direct_index;
     p->precise = !p->use_mfma && direct_index > kDirectPrecisionBudget;
+    // Distance from the nodes beyond which a pixel's sums take double-float
+    // logits: the MFMA kernel's room under its precision budget, the float32
+    // direct kernel's, none for double-float logits everywhere.
+    const double rh = p->radius * p->node_h;
+    if (p->use_mfma)
+        p->info.far_room = rh > 0.0 ? std::max(kFarRhoMin, kMfmaFarBudget / rh - p->radius) : INFINITY;
+    else if (!p->precise)
+        p->info.far_room = p->node_h > 0.0 ? std::sqrt(kDirectFarBudget / p->node_h) : INFINITY;
+    else
+        p->info.far_room = INFINITY;
+    p->far_rho2 = std::isfinite(p->info.far_room) ? (float)(p->info.far_room * p->info.far_room) : INFINITY;
     p->info.posterior_kernel = p->use_mfma ? 0 : (p->precise ? 2 : 1);
     if (hipMemcpy(p->d_tiles, tiles.data(), sizeof(float) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
         return HB_ERR_DEVICE;

@@ -81,7 +81,7 @@ class hb_plan_info_t(ctypes.Structure):
                 ("n_nodes", ctypes.c_int64), ("skip_log2", ctypes.c_double), ("skip_bound", ctypes.c_double),
                 ("mfma_index", ctypes.c_double), ("direct_index", ctypes.c_double),
                 ("band_log2", ctypes.c_double), ("band_chunks", ctypes.c_int64),
-                ("mfma_far_room", ctypes.c_double), ("mfma_df_constant", ctypes.c_int32),
+                ("far_room", ctypes.c_double), ("mfma_df_constant", ctypes.c_int32),
                 ("m_norm", ctypes.c_double),
                 ("k1_double_float", ctypes.c_int32)]
 
@@ -190,7 +190,7 @@ def hb_plan_get_info(plan: int) -> Dict[str, object]:
                 posterior_kernel=("mfma", "direct", "direct_precise")[info.posterior_kernel],
                 skip_log2=info.skip_log2, skip_bound=info.skip_bound, mfma_index=info.mfma_index,
                 direct_index=info.direct_index, band_log2=info.band_log2, band_chunks=info.band_chunks,
-                mfma_far_room=info.mfma_far_room, mfma_df_constant=bool(info.mfma_df_constant),
+                far_room=info.far_room, mfma_df_constant=bool(info.mfma_df_constant),
                 m_norm=info.m_norm,
                 k1_double_float=bool(info.k1_double_float))
 

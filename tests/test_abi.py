@@ -53,7 +53,7 @@ int main(void) {
   F(hb_plan_desc_t, thb_min) F(hb_plan_desc_t, lambda) F(hb_plan_desc_t, ref_thb)
   F(hb_plan_desc_t, lowpass) F(hb_plan_desc_t, grid_split) F(hb_plan_desc_t, illumination) F(hb_plan_desc_t, posterior_tolerance)
   F(hb_forward_model_t, eps_hb) F(hb_forward_model_t, path_length_cm)
-  F(hb_plan_info_t, gamma) F(hb_plan_info_t, grid_split) F(hb_plan_info_t, posterior_kernel) F(hb_plan_info_t, n_nodes) F(hb_plan_info_t, skip_log2) F(hb_plan_info_t, skip_bound) F(hb_plan_info_t, mfma_index) F(hb_plan_info_t, direct_index) F(hb_plan_info_t, band_log2) F(hb_plan_info_t, band_chunks) F(hb_plan_info_t, mfma_far_room) F(hb_plan_info_t, mfma_df_constant) F(hb_plan_info_t, m_norm) F(hb_plan_info_t, k1_double_float)
+  F(hb_plan_info_t, gamma) F(hb_plan_info_t, grid_split) F(hb_plan_info_t, posterior_kernel) F(hb_plan_info_t, n_nodes) F(hb_plan_info_t, skip_log2) F(hb_plan_info_t, skip_bound) F(hb_plan_info_t, mfma_index) F(hb_plan_info_t, direct_index) F(hb_plan_info_t, band_log2) F(hb_plan_info_t, band_chunks) F(hb_plan_info_t, far_room) F(hb_plan_info_t, mfma_df_constant) F(hb_plan_info_t, m_norm) F(hb_plan_info_t, k1_double_float)
   return 0;
 }
 """)

@@ -161,10 +161,10 @@ def _far_frames(h, w, n, region):
     return np.stack(out)
 
 
-def _far_run(run, frames):
+def _far_run(run, frames, kernel="mfma", room=3.0):
     from paper_1706_07263_amd import hb
     info = run.plan.info()
-    assert info["posterior_kernel"] == "mfma" and info["mfma_far_room"] == 3.0, info
+    assert info["posterior_kernel"] == kernel and info["far_room"] == pytest.approx(room, rel=1e-12), info
     hb.hb_plan_set_timing(run.plan.handle, True)
     gpu = run(frames)
     far = hb.hb_plan_get_far_pixels(run.plan.handle)
@@ -188,6 +188,22 @@ def test_far_observations_take_double_float_sums(torch_cuda):
     assert 640 * split <= far <= 650 * split, (far, split)
     ora = hbtest.run_oracle(frames, "f32", s)
     err = hbtest.assert_maps_close(gpu, ora, "far observations")
+    print("far pixels", far, {k: f"{v:.2e}" for k, v in err.items()})
+
+
+def test_far_observations_direct_kernel(torch_cuda):
+    """The float32 direct kernel (a 16^2 grid at sigma 0.01, node spacing
+    12 uM) forms the sums of the same dimmed region again with double-float
+    logits: its room is sqrt(1000 / 12) = 9.1 scaled units, the region lies
+    at least 18.7 from the nodes by the oracle's grid, the rest within 1.9."""
+    frames = _far_frames(96, 128, 1, (slice(16, 48), slice(16, 96)))
+    s = _settings(levels=1, grid=16, sigma=0.01)
+    run = hbtest.GpuRun(128, 96, s)
+    gpu, far = _far_run(run, frames, kernel="direct", room=math.sqrt(1000.0 / 12.0))
+    split = run.plan.info()["grid_split"]
+    run.close()
+    assert 640 * split <= far <= 650 * split, (far, split)
+    err = hbtest.assert_maps_close(gpu, hbtest.run_oracle(frames, "f32", s), "far observations, direct kernel")
     print("far pixels", far, {k: f"{v:.2e}" for k, v in err.items()})
 
 
