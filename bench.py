@@ -58,8 +58,8 @@ NOMINAL_CEILING_PAIRS_PER_S = 256 * N_SIMD * CLOCK_HZ / CHUNK_BLOCK_CYCLES      
 # rocprofv3 FETCH_SIZE/WRITE_SIZE runs summarised in profiles/, valid for the
 # device sources whose combined sha256 (kernel_source_sha) starts with
 # PROFILED_KERNEL_SHA; reported as null for any other source or workload.
-PROFILED_KERNEL_SHA = "ea7a3e95b40adbc1"
-PROFILED_POSTERIOR_TRAFFIC = 1208.6e6
+PROFILED_KERNEL_SHA = "53f13351ed65cd57"
+PROFILED_POSTERIOR_TRAFFIC = 1186.5e6
 KERNEL_SOURCES = ("hb_kernels.hip", "hb_internal.h", "hb_df.h")
 
 
